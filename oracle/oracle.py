@@ -1,0 +1,246 @@
+"""ctypes front end of the FP64 CPU oracle (trd_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark import this module; the product path never does.  It takes
+the plain parameter dict of a workload and numpy arrays, and shares no code
+with the HIP library or its binding.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "trd_oracle.c")
+_LIB = os.path.join(_HERE, "libtrd_oracle.so")
+
+ST_STOP_SNP, ST_ROT_FAIL, ST_OUT_OF_Z, ST_BAD_INPUT = 1, 2, 4, 32
+FL_P1, FL_P2, FL_P3, FL_P4 = 1, 2, 4, 8
+
+
+class OCfg(C.Structure):
+    _fields_ = [
+        ("x_layer", C.c_double * 6),
+        ("tilt", C.c_double * 6),
+        ("z_min", C.c_double), ("pad_len", C.c_double),
+        ("y_bin_w", C.c_double), ("drift_len", C.c_double),
+        ("dx_chamber", C.c_double * 540),
+        ("bz", C.c_double), ("x_over_x0", C.c_double), ("mass", C.c_double),
+        ("sigma_y", C.c_double * 3), ("sigma_dy", C.c_double * 3), ("tan_psi", C.c_double),
+        ("chi2_max", C.c_double), ("n_sigma_dy", C.c_double), ("n_sigma_road", C.c_double),
+        ("snp_max", C.c_double),
+        ("m_rel", C.c_double), ("m_len", C.c_double), ("m_dy", C.c_double),
+        ("m_chi2", C.c_double), ("m_snp", C.c_double),
+        ("n_rows", C.c_int32), ("n_yb", C.c_int32),
+    ]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-std=gnu11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        dp, ip, up, lp = (C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                          C.POINTER(C.c_uint32), C.POINTER(C.c_int64))
+        L.oracle_cfg_size.restype = C.c_int32
+        L.oracle_bin.argtypes = [C.POINTER(OCfg), C.c_int64, dp, dp, dp, up, ip, C.c_int32, ip, up]
+        L.oracle_match.argtypes = ([C.POINTER(OCfg), C.c_int64, dp, dp, dp, ip, ip,
+                                    C.c_int64, dp, dp, dp, up, ip, C.c_int32, C.c_int32, C.c_int32,
+                                    ip, dp, dp, dp, ip, dp, dp, ip, up, up, ip, lp, dp, dp, dp, ip])
+        L.oracle_propagate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
+        L.oracle_rotate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
+        L.oracle_add_ms.argtypes = [C.POINTER(OCfg), dp, dp]
+        L.oracle_update.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.oracle_ldl_pd.argtypes = [dp]
+        L.oracle_key.argtypes = [C.POINTER(OCfg), C.c_double, C.c_double, C.c_double, C.c_uint32,
+                                 C.c_int32, C.c_int32]
+        L.oracle_key.restype = C.c_int64
+        assert L.oracle_cfg_size() == C.sizeof(OCfg), "oracle config layout mismatch"
+        _lib = L
+    return _lib
+
+
+def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0):
+    c = OCfg()
+    P = params
+    for l in range(6):
+        c.x_layer[l] = P["x_layer"][l]
+        c.tilt[l] = P["tilt"][l]
+    c.z_min, c.pad_len = P["z_min"], P["pad_len"]
+    c.y_bin_w, c.drift_len = P["y_bin_w"], P["drift_len"]
+    for d in range(540):
+        c.dx_chamber[d] = float(P["dx_chamber"][d])
+    c.bz, c.x_over_x0, c.mass = P["bz"], P["x_over_x0"], P["mass"]
+    for k in range(3):
+        c.sigma_y[k] = P["sigma_y"][k]
+        c.sigma_dy[k] = P["sigma_dy"][k]
+    c.tan_psi = P["tan_psi"]
+    c.chi2_max, c.n_sigma_dy = P["chi2_max"], P["n_sigma_dy"]
+    c.n_sigma_road, c.snp_max = P["n_sigma_road"], P["snp_max"]
+    c.m_rel, c.m_len, c.m_dy, c.m_chi2, c.m_snp = margin_rel, m_len, m_dy, m_chi2, m_snp
+    c.n_rows, c.n_yb = P["n_rows"], P["n_yb"]
+    return c
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def bin_tracklets(params, w):
+    """Sorted permutation and cell offsets of the workload's tracklets."""
+    L = lib()
+    cfg = make_cfg(params)
+    n = int(w["tkl_y"].size)
+    ng = int(w.get("n_groups", 1))
+    nc = ng * 540 * params["n_rows"] * params["n_yb"]
+    y, z, dy = _f64(w["tkl_y"]), _f64(w["tkl_z"]), _f64(w["tkl_dy"])
+    dr = np.ascontiguousarray(w["tkl_det_row"], dtype=np.uint32)
+    g = np.ascontiguousarray(w["tkl_group"], dtype=np.int32) if "tkl_group" in w else None
+    perm = np.zeros(max(n, 1), np.int32)
+    off = np.zeros(nc + 1, np.uint32)
+    rc = L.oracle_bin(C.byref(cfg), n, _ptr(y, C.c_double), _ptr(z, C.c_double), _ptr(dy, C.c_double),
+                      _ptr(dr, C.c_uint32), _ptr(g, C.c_int32), ng, _ptr(perm, C.c_int32),
+                      _ptr(off, C.c_uint32))
+    assert rc == 0
+    return perm[:n], off
+
+
+def match(params, w, *, mode="binned", threads=0, layers=False, margins=None, track_slice=None):
+    """Run the oracle on a workload dict (see synth.generate).
+
+    margins: dict(margin_rel, m_len, m_dy, m_chi2, m_snp) for the decision
+    flags.  track_slice: optional index array of tracks to process (the rest
+    of the workload's tracklets stay in the search).
+    Returns a dict of numpy outputs.
+    """
+    L = lib()
+    cfg = make_cfg(params, **(margins or {}))
+    tp, tc, tx = _f64(w["p"]), _f64(w["cov"]), _f64(w["x"])
+    ts = np.ascontiguousarray(w["sector"], dtype=np.int32)
+    tg = np.ascontiguousarray(w["group"], dtype=np.int32) if "group" in w else None
+    if track_slice is not None:
+        sl = np.asarray(track_slice)
+        tp, tc, tx, ts = (np.ascontiguousarray(tp[:, sl]), np.ascontiguousarray(tc[:, sl]),
+                          np.ascontiguousarray(tx[sl]), np.ascontiguousarray(ts[sl]))
+        tg = np.ascontiguousarray(tg[sl]) if tg is not None else None
+    n = int(tx.size)
+    y, z, dy = _f64(w["tkl_y"]), _f64(w["tkl_z"]), _f64(w["tkl_dy"])
+    dr = np.ascontiguousarray(w["tkl_det_row"], dtype=np.uint32)
+    kg = np.ascontiguousarray(w["tkl_group"], dtype=np.int32) if "tkl_group" in w else None
+    ng = int(w.get("n_groups", 1))
+    o = dict(
+        idx=np.zeros((6, n), np.int32), p=np.zeros((5, n)), cov=np.zeros((15, n)),
+        x=np.zeros(n), sector=np.zeros(n, np.int32), chi2=np.zeros(n),
+        chi2_layer=np.zeros((6, n)), n_match=np.zeros(n, np.int32),
+        status=np.zeros(n, np.uint32), flags=np.zeros(n, np.uint32),
+        flag_layer=np.zeros(n, np.int32), n_cand=np.zeros(n, np.int64),
+    )
+    if layers:
+        o.update(lp=np.zeros((6, 5, n)), lc=np.zeros((6, 15, n)), lx=np.zeros((6, n)),
+                 lsec=np.zeros((6, n), np.int32))
+    dp, ip, up = C.c_double, C.c_int32, C.c_uint32
+    rc = L.oracle_match(
+        C.byref(cfg), n, _ptr(tp, dp), _ptr(tc, dp), _ptr(tx, dp), _ptr(ts, ip), _ptr(tg, ip),
+        int(y.size), _ptr(y, dp), _ptr(z, dp), _ptr(dy, dp), _ptr(dr, up), _ptr(kg, ip), ng,
+        1 if mode == "brute" else 0, int(threads),
+        _ptr(o["idx"], ip), _ptr(o["p"], dp), _ptr(o["cov"], dp), _ptr(o["x"], dp),
+        _ptr(o["sector"], ip), _ptr(o["chi2"], dp), _ptr(o["chi2_layer"], dp),
+        _ptr(o["n_match"], ip), _ptr(o["status"], up), _ptr(o["flags"], up),
+        _ptr(o["flag_layer"], ip), _ptr(o["n_cand"], C.c_int64),
+        _ptr(o.get("lp"), dp), _ptr(o.get("lc"), dp), _ptr(o.get("lx"), dp), _ptr(o.get("lsec"), ip))
+    assert rc == 0, rc
+    return o
+
+
+# ---- single steps -----------------------------------------------------------
+
+def _cfg_only(params):
+    return make_cfg(params)
+
+
+def propagate(params, p, cov, x, x2, want_j=False):
+    """One helix step.  Returns (ok, p, cov, x, J)."""
+    L = lib()
+    cfg = _cfg_only(params)
+    p = _f64(p).copy()
+    cv = _f64(cov).copy() if cov is not None else None
+    xx = np.array([x], dtype=np.float64)
+    J = np.zeros(25)
+    ok = L.oracle_propagate(C.byref(cfg), _ptr(p, C.c_double), _ptr(cv, C.c_double),
+                            _ptr(xx, C.c_double), float(x2), _ptr(J, C.c_double))
+    return bool(ok), p, cv, float(xx[0]), J.reshape(5, 5)
+
+
+def rotate(params, p, cov, x, da):
+    L = lib()
+    cfg = _cfg_only(params)
+    p = _f64(p).copy()
+    cv = _f64(cov).copy() if cov is not None else None
+    xx = np.array([x], dtype=np.float64)
+    J = np.zeros(25)
+    ok = L.oracle_rotate(C.byref(cfg), _ptr(p, C.c_double), _ptr(cv, C.c_double),
+                         _ptr(xx, C.c_double), float(da), _ptr(J, C.c_double))
+    return bool(ok), p, cv, float(xx[0]), J.reshape(5, 5)
+
+
+def add_ms(params, p, cov):
+    L = lib()
+    cfg = _cfg_only(params)
+    p = _f64(p).copy()
+    cv = _f64(cov).copy()
+    L.oracle_add_ms(C.byref(cfg), _ptr(p, C.c_double), _ptr(cv, C.c_double))
+    return cv
+
+
+def update(p, cov, ry, rz, tau, vy, vz):
+    L = lib()
+    p = _f64(p).copy()
+    cv = _f64(cov).copy()
+    L.oracle_update(_ptr(p, C.c_double), _ptr(cv, C.c_double), ry, rz, tau, vy, vz)
+    return p, cv
+
+
+def ldl_pd(cov):
+    return bool(lib().oracle_ldl_pd(_ptr(_f64(cov).copy(), C.c_double)))
+
+
+def key(params, y, z, dy, det_row, grp=0, n_groups=1):
+    cfg = _cfg_only(params)
+    return int(lib().oracle_key(C.byref(cfg), y, z, dy, det_row, grp, n_groups))
+
+
+def unpack(pk):
+    """Packed upper-triangular 15-vector -> symmetric 5x5 (numpy, for tests)."""
+    M = np.zeros((5, 5))
+    k = 0
+    for i in range(5):
+        for j in range(i, 5):
+            M[i, j] = M[j, i] = pk[k]
+            k += 1
+    return M
+
+
+def pack(M):
+    return np.array([M[i, j] for i in range(5) for j in range(i, 5)])

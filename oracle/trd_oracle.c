@@ -1,0 +1,786 @@
+/*
+ * FP64 CPU oracle of TRD tracklet-to-track matching.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no source with the HIP library.
+ *
+ * What it computes, following Sect. 3 of the paper ("TRD tracking
+ * algorithm") step by step and in plain double precision:
+ *
+ *   for every seed track (independently; the paper parallelises over tracks)
+ *     for layer l = 0..5
+ *       propagate the helix state and covariance to the layer radius
+ *       (the "maximal precision" step of Sect. 3, here a uniform field);
+ *       rotate into the neighbouring sector if the point left the sector;
+ *       add multiple scattering of the layer;
+ *       open a search road from the covariance (Sect. 3, tracklets "inside a
+ *       search road based on the covariance matrices");
+ *       for every tracklet in the road: linear extrapolation to the
+ *       tracklet radius, pad-tilt corrected y residual (Sect. 3, last
+ *       paragraph), dy exclusion beyond 4 sigma, chi2 from y and z only;
+ *       keep the best hypothesis (N_candidates = 1), propagate precisely to
+ *       its radius and apply the Kalman update.
+ *
+ * Readings where the paper is silent (all shared with the HIP path by
+ * specification, not by code):
+ *   - propagation is the exact helix map in (y, z, sin phi, tan lambda, q/pT)
+ *     with its exact Jacobian; curvature C = -kappa * Bz * q/pT so that
+ *     sin phi grows by C per cm of x;
+ *   - one thin scatterer per layer, Highland width, pion mass;
+ *   - tracklet resolutions are second-order polynomials in sin phi, the dy
+ *     gate width adds the track slope error: sqrt(s_dy^2 + L^2 C_ss / f^6);
+ *   - road half widths n_road * sqrt(S_yy), n_road * sqrt(S_zz) around the
+ *     prediction; chi2 <= chi2_max; winner = lexicographic min (chi2, index);
+ *   - tracklet cells: key = ((group*540 + det)*n_rows + row)*n_yb + ybin,
+ *     ybin = clamp(floor((y - y_min) * (1/w)), 0, n_yb-1) in double.
+ *
+ * Decision-margin flags mark tracks where a gate, tie or geometric decision
+ * lies within a margin, so that a correct implementation in a different
+ * precision may legitimately decide differently there.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NLAY 6
+#define NSEC 18
+#define NSTK 5
+#define NDET 540
+
+/* status bits */
+#define ST_STOP_SNP 1u
+#define ST_ROT_FAIL 2u
+#define ST_OUT_OF_Z 4u
+#define ST_BAD_INPUT 32u
+/* decision-margin flags */
+#define FL_P1 1u /* winner near one of its gates */
+#define FL_P2 2u /* a loser fails exactly one gate by a margin and would win */
+#define FL_P3 4u /* near tie between winner and runner-up */
+#define FL_P4 8u /* sector edge, z acceptance or sin(phi) limit near */
+
+typedef struct {
+    double x_layer[NLAY];
+    double tilt[NLAY];          /* tan of the pad tilt angle per layer */
+    double z_min, pad_len;
+    double y_bin_w;             /* power of two, cm */
+    double drift_len;
+    double dx_chamber[NDET];
+    double bz, x_over_x0, mass;
+    double sigma_y[3], sigma_dy[3], tan_psi;
+    double chi2_max, n_sigma_dy, n_sigma_road, snp_max;
+    double m_rel, m_len, m_dy, m_chi2, m_snp; /* decision margins */
+    int32_t n_rows, n_yb;
+} ocfg;
+
+static const double KAPPA = 2.99792458e-3;
+
+/* ---------------------------------------------------------------------- */
+/* small dense helpers                                                     */
+/* ---------------------------------------------------------------------- */
+
+static void unpack(const double *pk, double C[5][5])
+{
+    int k = 0;
+    for (int i = 0; i < 5; i++)
+        for (int j = i; j < 5; j++) {
+            C[i][j] = pk[k];
+            C[j][i] = pk[k];
+            k++;
+        }
+}
+
+static void pack(double C[5][5], double *pk)
+{
+    int k = 0;
+    for (int i = 0; i < 5; i++)
+        for (int j = i; j < 5; j++)
+            pk[k++] = C[i][j];
+}
+
+/* C <- J C J^T, with full 5x5 products */
+static void transport(double J[5][5], double C[5][5])
+{
+    double T[5][5], R[5][5];
+    for (int i = 0; i < 5; i++)
+        for (int j = 0; j < 5; j++) {
+            double a = 0;
+            for (int k = 0; k < 5; k++) a += J[i][k] * C[k][j];
+            T[i][j] = a;
+        }
+    for (int i = 0; i < 5; i++)
+        for (int j = 0; j < 5; j++) {
+            double a = 0;
+            for (int k = 0; k < 5; k++) a += T[i][k] * J[j][k];
+            R[i][j] = a;
+        }
+    /* symmetrise exactly: the two halves differ only by rounding order */
+    for (int i = 0; i < 5; i++)
+        for (int j = i; j < 5; j++) {
+            double v = 0.5 * (R[i][j] + R[j][i]);
+            C[i][j] = v;
+            C[j][i] = v;
+        }
+}
+
+static void identity(double J[5][5])
+{
+    memset(J, 0, sizeof(double) * 25);
+    for (int i = 0; i < 5; i++) J[i][i] = 1.0;
+}
+
+static double sinc(double u) { return u == 0.0 ? 1.0 : sin(u) / u; }
+
+/* (sin d - d) / d^2, by its Taylor series where the direct form cancels */
+static double g_of(double d)
+{
+    if (fabs(d) < 0.5) {
+        double d2 = d * d, term = -d / 6.0, sum = 0.0;
+        for (int k = 1; k <= 8; k++) {
+            sum += term;
+            term *= -d2 / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+        }
+        return sum;
+    }
+    return (sin(d) - d) / (d * d);
+}
+
+static int near_lim(double a, double lim, double rel, double abs_)
+{
+    return fabs(a - lim) <= rel * fabs(lim) + abs_;
+}
+
+/* ---------------------------------------------------------------------- */
+/* helix propagation in the sector frame                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Moves the state from *x to x2 along the helix.  Returns 0 (state
+ * untouched) if |sin phi| would reach snp_max.  J (optional) receives the
+ * Jacobian d p(x2) / d p(x). */
+static int propagate(double p[5], double C[5][5], double *x, double x2,
+                     const ocfg *g, unsigned *flags, double Jout[5][5])
+{
+    double dx = x2 - *x;
+    double k = -KAPPA * g->bz;            /* d curvature / d (q/pT) */
+    double cu = k * p[4];                 /* signed curvature, 1/cm */
+    double s1 = p[2];
+    double s2 = s1 + cu * dx;
+    if (flags && near_lim(fabs(s2), g->snp_max, g->m_rel, g->m_snp)) *flags |= FL_P4;
+    if (!(fabs(s2) < g->snp_max)) return 0;
+    double f1 = sqrt(1.0 - s1 * s1);
+    double f2 = sqrt(1.0 - s2 * s2);
+    double t = p[3];
+    /* transverse displacement: integral of tan(phi) dx, written without 1/C */
+    double dy = dx * (s1 + s2) / (f1 + f2);
+    /* arc length from the chord */
+    double chord = sqrt(dx * dx + dy * dy);
+    double h = 0.5 * fabs(cu) * chord;
+    double arc = (dx >= 0 ? chord : -chord) * (h > 0 ? asin(h) / h : 1.0);
+    double delta = cu * arc;              /* turning angle */
+
+    double J[5][5];
+    identity(J);
+    J[0][2] = arc * sinc(delta) / (f1 * f2);
+    J[0][4] = k * dx * dx / (f1 + f2) * (1.0 + s2 * (s1 + s2) / (f2 * (f1 + f2)));
+    J[1][2] = t * dy / (f1 * f2);
+    J[1][3] = arc;
+    {
+        double sh = sinc(0.5 * delta);
+        J[1][4] = k * t * arc * arc * ((s2 / f2) * sh * sh * 0.5 + g_of(delta));
+    }
+    J[2][4] = k * dx;
+
+    p[0] += dy;
+    p[1] += t * arc;
+    p[2] = s2;
+    *x = x2;
+    if (C) transport(J, C);
+    if (Jout) memcpy(Jout, J, sizeof(J));
+    return 1;
+}
+
+/* Rotates the frame by da (alpha' = alpha + da) at the current point.
+ * Returns 0 if the track would move inwards in the new frame. */
+static int rotate(double p[5], double C[5][5], double *x, double da,
+                  const ocfg *g, double Jout[5][5])
+{
+    double ca = cos(da), sa = sin(da);
+    double s = p[2], f = sqrt(1.0 - s * s);
+    double s1 = s * ca - f * sa;
+    double f1 = f * ca + s * sa;
+    if (!(f1 > 0.0)) return 0;
+    double x1 = *x * ca + p[0] * sa;
+    double y1 = -*x * sa + p[0] * ca;
+    double cu = -KAPPA * g->bz * p[4];
+    double J[5][5];
+    identity(J);
+    J[0][0] = f / f1;
+    J[1][0] = -sa * p[3] / f1;
+    J[2][0] = -cu * sa;
+    J[2][2] = f1 / f;
+    p[0] = y1;
+    p[2] = s1;
+    *x = x1;
+    if (C) transport(J, C);
+    if (Jout) memcpy(Jout, J, sizeof(J));
+    return 1;
+}
+
+/* Thin scatterer of thickness x_over_x0 crossed at the current point. */
+static void add_ms(const double p[5], double C[5][5], const ocfg *g)
+{
+    double s = p[2], t = p[3], c = p[4];
+    if (c == 0.0 || g->x_over_x0 <= 0.0) return;
+    double f = sqrt(1.0 - s * s);
+    double tt = 1.0 + t * t;
+    double pp = sqrt(tt) / fabs(c);
+    double beta = pp / sqrt(pp * pp + g->mass * g->mass);
+    double xi = g->x_over_x0 * sqrt(tt) / f;
+    double th0 = 0.0136 / (beta * pp) * sqrt(xi) * (1.0 + 0.038 * log(xi));
+    double th2 = th0 * th0;
+    C[2][2] += th2 * f * f * tt;
+    C[3][3] += th2 * tt * tt;
+    C[4][4] += th2 * c * c * t * t;
+    C[3][4] += th2 * tt * c * t;
+    C[4][3] = C[3][4];
+}
+
+/* Kalman update with the measurement m = (y_tkl, z_tkl) of the model
+ * h(p) = (y + tau (z - z_tkl), z); r = m - h(p).  Joseph form. */
+static void kalman_update(double p[5], double C[5][5], double ry, double rz,
+                          double tau, double vy, double vz)
+{
+    double H[2][5] = {{1, tau, 0, 0, 0}, {0, 1, 0, 0, 0}};
+    double V[2][2] = {{vy, 0}, {0, vz}};
+    double CHt[5][2], S[2][2], Si[2][2], K[5][2];
+    for (int i = 0; i < 5; i++)
+        for (int a = 0; a < 2; a++) {
+            double v = 0;
+            for (int k = 0; k < 5; k++) v += C[i][k] * H[a][k];
+            CHt[i][a] = v;
+        }
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            double v = V[a][b];
+            for (int k = 0; k < 5; k++) v += H[a][k] * CHt[k][b];
+            S[a][b] = v;
+        }
+    double det = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+    Si[0][0] = S[1][1] / det;
+    Si[1][1] = S[0][0] / det;
+    Si[0][1] = -S[0][1] / det;
+    Si[1][0] = -S[1][0] / det;
+    for (int i = 0; i < 5; i++)
+        for (int b = 0; b < 2; b++)
+            K[i][b] = CHt[i][0] * Si[0][b] + CHt[i][1] * Si[1][b];
+    for (int i = 0; i < 5; i++) p[i] += K[i][0] * ry + K[i][1] * rz;
+
+    double A[5][5], T[5][5], R[5][5];
+    for (int i = 0; i < 5; i++)
+        for (int j = 0; j < 5; j++)
+            A[i][j] = (i == j ? 1.0 : 0.0) - (K[i][0] * H[0][j] + K[i][1] * H[1][j]);
+    for (int i = 0; i < 5; i++)
+        for (int j = 0; j < 5; j++) {
+            double v = 0;
+            for (int k = 0; k < 5; k++) v += A[i][k] * C[k][j];
+            T[i][j] = v;
+        }
+    for (int i = 0; i < 5; i++)
+        for (int j = 0; j < 5; j++) {
+            double v = 0;
+            for (int k = 0; k < 5; k++) v += T[i][k] * A[j][k];
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 2; b++) v += K[i][a] * V[a][b] * K[j][b];
+            R[i][j] = v;
+        }
+    for (int i = 0; i < 5; i++)
+        for (int j = i; j < 5; j++) {
+            double v = 0.5 * (R[i][j] + R[j][i]);
+            C[i][j] = v;
+            C[j][i] = v;
+        }
+}
+
+/* Positive definiteness by an LDL^T factorisation. */
+static int ldl_pd(double C[5][5])
+{
+    double L[5][5] = {{0}}, d[5];
+    for (int j = 0; j < 5; j++) {
+        double v = C[j][j];
+        for (int k = 0; k < j; k++) v -= L[j][k] * L[j][k] * d[k];
+        if (!(v > 0.0)) return 0;
+        d[j] = v;
+        L[j][j] = 1.0;
+        for (int i = j + 1; i < 5; i++) {
+            double w = C[i][j];
+            for (int k = 0; k < j; k++) w -= L[i][k] * L[j][k] * d[k];
+            L[i][j] = w / v;
+        }
+    }
+    return 1;
+}
+
+static double poly2(const double a[3], double s) { return a[0] + a[1] * s + a[2] * s * s; }
+
+/* ---------------------------------------------------------------------- */
+/* tracklet cells                                                          */
+/* ---------------------------------------------------------------------- */
+
+static int64_t n_cells_of(const ocfg *g, int32_t n_groups)
+{
+    return (int64_t)n_groups * NDET * g->n_rows * g->n_yb;
+}
+
+static int ybin_of(const ocfg *g, double y)
+{
+    double ymin = -g->y_bin_w * g->n_yb / 2.0;
+    double u = floor((y - ymin) * (1.0 / g->y_bin_w));
+    if (u < 0) return 0;
+    if (u > g->n_yb - 1) return g->n_yb - 1;
+    return (int)u;
+}
+
+/* Cell key of one tracklet; the invalid ones get n_cells (placed last). */
+static int64_t tkl_key(const ocfg *g, double y, double z, double dy, uint32_t det_row,
+                       int32_t grp, int32_t n_groups)
+{
+    uint32_t det = det_row >> 5, row = det_row & 31u;
+    if (det >= NDET || (int32_t)row >= g->n_rows || grp < 0 || grp >= n_groups ||
+        !isfinite(y) || !isfinite(z) || !isfinite(dy))
+        return n_cells_of(g, n_groups);
+    return (((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_yb + ybin_of(g, y);
+}
+
+typedef struct { int64_t key; int64_t idx; } keyidx;
+
+static int cmp_keyidx(const void *a, const void *b)
+{
+    const keyidx *u = (const keyidx *)a, *v = (const keyidx *)b;
+    if (u->key != v->key) return u->key < v->key ? -1 : 1;
+    if (u->idx != v->idx) return u->idx < v->idx ? -1 : 1;
+    return 0;
+}
+
+/* Stable counting sort by cell: perm[] lists input indices in (key, index)
+ * order; offsets[c] is the first sorted position of cell c and
+ * offsets[n_cells] the number of valid tracklets. */
+int oracle_bin(const ocfg *g, int64_t n, const double *y, const double *z, const double *dy,
+               const uint32_t *det_row, const int32_t *grp, int32_t n_groups,
+               int32_t *perm, uint32_t *offsets)
+{
+    int64_t nc = n_cells_of(g, n_groups);
+    keyidx *ki = (keyidx *)malloc(sizeof(keyidx) * (size_t)(n > 0 ? n : 1));
+    if (!ki) return -2;
+    for (int64_t i = 0; i < n; i++) {
+        ki[i].key = tkl_key(g, y[i], z[i], dy[i], det_row[i], grp ? grp[i] : 0, n_groups);
+        ki[i].idx = i;
+    }
+    qsort(ki, (size_t)n, sizeof(keyidx), cmp_keyidx);
+    for (int64_t c = 0; c <= nc; c++) offsets[c] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        perm[i] = (int32_t)ki[i].idx;
+        if (ki[i].key < nc) offsets[ki[i].key + 1]++;
+    }
+    for (int64_t c = 0; c < nc; c++) offsets[c + 1] += offsets[c];
+    free(ki);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* per-track matching                                                      */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    const double *y, *z, *dy;
+    const uint32_t *det_row;
+    const int32_t *grp;
+    int64_t n;
+    const int32_t *perm;     /* binned mode */
+    const uint32_t *offsets; /* binned mode */
+    int32_t n_groups;
+    int brute;
+} otkl;
+
+typedef struct {
+    int32_t *idx;          /* [6][n] */
+    double *p, *c, *x;     /* [5][n], [15][n], [n] */
+    int32_t *sec;
+    double *chi2, *chi2_layer;   /* [n], [6][n] (optional) */
+    int32_t *n_match;
+    uint32_t *status, *flags;
+    int32_t *flag_layer;   /* optional: first layer holding a flag, 6 if none */
+    int64_t *n_cand;       /* optional: candidates looked at */
+    double *lp, *lc, *lx;  /* optional per-layer state: [6][5][n], [6][15][n], [6][n] */
+    int32_t *lsec;         /* optional [6][n] */
+} oout;
+
+/* prediction-side quantities of one layer's road */
+typedef struct {
+    double y, z, s, t, f, tphi, tz, tau;
+    double Ry, Rz, gdy, dytrk;
+    double Si[2][2];
+} road_t;
+
+/* Evaluates one candidate.  fail: bit0 y road, bit1 z road, bit2 dy gate,
+ * bit3 chi2 cut; nearm: same bits when the value lies within the margin of
+ * its limit. */
+static void eval_cand(const ocfg *g, const road_t *r, double yj, double zj, double dyj, double dxj,
+                      double *chi2, unsigned *fail, unsigned *nearm)
+{
+    double ye = r->y + dxj * r->tphi;
+    double ze = r->z + dxj * r->tz;
+    double ry = yj - (ye + r->tau * (ze - zj));
+    double rz = zj - ze;
+    double ddy = dyj - r->dytrk;
+    double c2 = r->Si[0][0] * ry * ry + 2.0 * r->Si[0][1] * ry * rz + r->Si[1][1] * rz * rz;
+    unsigned f = 0, nm = 0;
+    if (!(fabs(ry) <= r->Ry)) f |= 1u;
+    if (!(fabs(rz) <= r->Rz)) f |= 2u;
+    if (!(fabs(ddy) <= r->gdy)) f |= 4u;
+    if (!(c2 <= g->chi2_max)) f |= 8u;
+    if (near_lim(fabs(ry), r->Ry, g->m_rel, g->m_len)) nm |= 1u;
+    if (near_lim(fabs(rz), r->Rz, g->m_rel, g->m_len)) nm |= 2u;
+    if (near_lim(fabs(ddy), r->gdy, g->m_rel, g->m_dy)) nm |= 4u;
+    if (near_lim(c2, g->chi2_max, g->m_rel, g->m_chi2)) nm |= 8u;
+    *chi2 = c2;
+    *fail = f;
+    *nearm = nm;
+}
+
+static int popcount4(unsigned v) { return (v & 1) + ((v >> 1) & 1) + ((v >> 2) & 1) + ((v >> 3) & 1); }
+
+/* candidate list of one layer (indices into the input tracklet arrays) */
+typedef struct { int64_t *v; int64_t n, cap; } ilist;
+
+static void ilist_push(ilist *L, int64_t j)
+{
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 256;
+        L->v = (int64_t *)realloc(L->v, sizeof(int64_t) * (size_t)L->cap);
+    }
+    L->v[L->n++] = j;
+}
+
+static void gather_candidates(const ocfg *g, const otkl *T, const road_t *r, int grp, int sec, int l,
+                              double dxmax, ilist *L)
+{
+    L->n = 0;
+    if (T->brute) {
+        for (int64_t j = 0; j < T->n; j++) {
+            uint32_t det = T->det_row[j] >> 5, row = T->det_row[j] & 31u;
+            int32_t gj = T->grp ? T->grp[j] : 0;
+            if (det >= NDET || (int32_t)row >= g->n_rows || gj != grp) continue;
+            if (!isfinite(T->y[j]) || !isfinite(T->z[j]) || !isfinite(T->dy[j])) continue;
+            if ((int)(det / (NSTK * NLAY)) != sec || (int)(det % NLAY) != l) continue;
+            ilist_push(L, j);
+        }
+        return;
+    }
+    /* cells whose pad rows and y bins overlap the road (plus margins that
+     * cover misalignment, tilt and the decision margins) */
+    double slack_y = 2.0 * (g->m_rel * r->Ry + g->m_len) + 1e-3;
+    double slack_z = 2.0 * (g->m_rel * r->Rz + g->m_len) + 1e-3;
+    double mz = dxmax * fabs(r->tz);
+    double my = fabs(r->tau) * (r->Rz + mz + slack_z) + dxmax * fabs(r->tphi);
+    double zlo = r->z - r->Rz - mz - slack_z, zhi = r->z + r->Rz + mz + slack_z;
+    double ylo = r->y - r->Ry - my - slack_y, yhi = r->y + r->Ry + my + slack_y;
+    int nrt = NSTK * g->n_rows;
+    double glo = floor((zlo - g->z_min) / g->pad_len), ghi = floor((zhi - g->z_min) / g->pad_len);
+    if (glo < 0) glo = 0;
+    if (ghi > nrt - 1) ghi = nrt - 1;
+    int yb0 = ybin_of(g, ylo), yb1 = ybin_of(g, yhi);
+    for (int gr = (int)glo; gr <= (int)ghi; gr++) {
+        int stack = gr / g->n_rows, row = gr % g->n_rows;
+        int det = sec * (NSTK * NLAY) + stack * NLAY + l;
+        int64_t base = (((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_yb;
+        uint32_t a = T->offsets[base + yb0], b = T->offsets[base + yb1 + 1];
+        for (uint32_t k = a; k < b; k++) ilist_push(L, T->perm[k]);
+    }
+}
+
+static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, const double *ic,
+                      const double *ix, const int32_t *isec, const int32_t *igrp, const otkl *T,
+                      double dxmax, const oout *o, ilist *L)
+{
+    double p[5], C[5][5], pk[15], x = ix[i];
+    for (int k = 0; k < 5; k++) p[k] = ip[k * n + i];
+    for (int k = 0; k < 15; k++) pk[k] = ic[k * n + i];
+    unpack(pk, C);
+    int sec = isec[i], grp = igrp ? igrp[i] : 0;
+    unsigned status = 0, flags = 0;
+    int flag_layer = NLAY, nmatch = 0;
+    double chi2sum = 0.0;
+    int64_t ncand = 0;
+    const double tan10 = tan(M_PI / NSEC), dphi = 2.0 * M_PI / NSEC;
+    for (int l = 0; l < NLAY; l++) {
+        o->idx[l * n + i] = -1;
+        if (o->chi2_layer) o->chi2_layer[l * n + i] = 0.0;
+        if (o->lx) o->lx[l * n + i] = NAN;
+        if (o->lsec) o->lsec[l * n + i] = -1;
+    }
+
+    int bad = !(isfinite(x) && sec >= 0 && sec < NSEC && grp >= 0 && grp < T->n_groups);
+    for (int k = 0; k < 5; k++) bad |= !isfinite(p[k]);
+    for (int k = 0; k < 15; k++) bad |= !isfinite(pk[k]);
+    if (!bad) bad = !(fabs(p[2]) < g->snp_max) || !ldl_pd(C);
+    if (bad) {
+        status = ST_BAD_INPUT;
+        goto done;
+    }
+
+    for (int l = 0; l < NLAY; l++) {
+        unsigned lf = 0;
+        double xl = g->x_layer[l];
+        if (!propagate(p, C, &x, xl, g, &lf, NULL)) {
+            status |= ST_STOP_SNP;
+            flags |= lf;
+            if (lf && flag_layer == NLAY) flag_layer = l;
+            break;
+        }
+        /* sector containing the point (at most two hops) */
+        int stop = 0;
+        for (int nrot = 0;; nrot++) {
+            double ylim = xl * tan10;
+            if (near_lim(fabs(p[0]), ylim, g->m_rel, g->m_len)) lf |= FL_P4;
+            if (fabs(p[0]) <= ylim) break;
+            if (nrot == 2) { status |= ST_ROT_FAIL; stop = 1; break; }
+            int up = p[0] > 0;
+            if (!rotate(p, C, &x, up ? dphi : -dphi, g, NULL)) { status |= ST_ROT_FAIL; stop = 1; break; }
+            sec = (sec + (up ? 1 : NSEC - 1)) % NSEC;
+            if (!propagate(p, C, &x, xl, g, &lf, NULL)) { status |= ST_STOP_SNP; stop = 1; break; }
+        }
+        if (stop) {
+            flags |= lf;
+            if (lf && flag_layer == NLAY) flag_layer = l;
+            break;
+        }
+        add_ms(p, C, g);
+
+        /* road from the covariance */
+        road_t r;
+        r.y = p[0]; r.z = p[1]; r.s = p[2]; r.t = p[3];
+        r.f = sqrt(1.0 - r.s * r.s);
+        r.tphi = r.s / r.f;
+        r.tz = r.t / r.f;
+        r.tau = g->tilt[l];
+        double sy = poly2(g->sigma_y, r.s);
+        double vy = sy * sy, vz = g->pad_len * g->pad_len / 12.0;
+        double Syy = C[0][0] + 2.0 * r.tau * C[0][1] + r.tau * r.tau * C[1][1] + vy;
+        double Syz = C[0][1] + r.tau * C[1][1];
+        double Szz = C[1][1] + vz;
+        double det = Syy * Szz - Syz * Syz;
+        r.Si[0][0] = Szz / det;
+        r.Si[1][1] = Syy / det;
+        r.Si[0][1] = r.Si[1][0] = -Syz / det;
+        r.Ry = g->n_sigma_road * sqrt(Syy);
+        r.Rz = g->n_sigma_road * sqrt(Szz);
+        r.dytrk = g->drift_len * (r.tphi - g->tan_psi);
+        {
+            double sdy = poly2(g->sigma_dy, r.s);
+            double f3 = r.f * r.f * r.f;
+            r.gdy = g->n_sigma_dy * sqrt(sdy * sdy + g->drift_len * g->drift_len * C[2][2] / (f3 * f3));
+        }
+
+        /* z acceptance of the whole search window */
+        double mz = dxmax * fabs(r.tz);
+        double wlo = r.z - r.Rz - mz, whi = r.z + r.Rz + mz, zmax = -g->z_min;
+        if (near_lim(whi, g->z_min, g->m_rel, g->m_len) || near_lim(wlo, zmax, g->m_rel, g->m_len)) lf |= FL_P4;
+        if (whi < g->z_min || wlo > zmax) {
+            status |= ST_OUT_OF_Z;
+        } else {
+            gather_candidates(g, T, &r, grp, sec, l, dxmax, L);
+            ncand += L->n;
+            int64_t best = -1, best_orig = -1;
+            double bchi = 0.0, second = INFINITY;
+            unsigned bnear = 0;
+            for (int64_t a = 0; a < L->n; a++) {
+                int64_t j = L->v[a];
+                double c2;
+                unsigned fail, nm;
+                eval_cand(g, &r, T->y[j], T->z[j], T->dy[j], g->dx_chamber[T->det_row[j] >> 5], &c2, &fail, &nm);
+                if (fail) continue;
+                if (best < 0 || c2 < bchi || (c2 == bchi && j < best_orig)) {
+                    if (best >= 0) second = bchi < second ? bchi : second;
+                    best = a; best_orig = j; bchi = c2; bnear = nm;
+                } else if (c2 < second) {
+                    second = c2;
+                }
+            }
+            if (best >= 0) {
+                if (bnear) lf |= FL_P1;
+                if (second - bchi <= g->m_rel * bchi + g->m_chi2) lf |= FL_P3;
+            }
+            /* a rejected candidate one marginal gate away from winning */
+            for (int64_t a = 0; a < L->n; a++) {
+                int64_t j = L->v[a];
+                double c2;
+                unsigned fail, nm;
+                eval_cand(g, &r, T->y[j], T->z[j], T->dy[j], g->dx_chamber[T->det_row[j] >> 5], &c2, &fail, &nm);
+                if (!fail || popcount4(fail) != 1 || !(fail & nm)) continue;
+                if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2) lf |= FL_P2;
+            }
+            if (best >= 0) {
+                int64_t j = best_orig;
+                double dxj = g->dx_chamber[T->det_row[j] >> 5];
+                if (dxj != 0.0) {
+                    if (!propagate(p, C, &x, xl + dxj, g, &lf, NULL)) {
+                        status |= ST_STOP_SNP;
+                        flags |= lf;
+                        if (lf && flag_layer == NLAY) flag_layer = l;
+                        break;
+                    }
+                }
+                double ry = T->y[j] - (p[0] + r.tau * (p[1] - T->z[j]));
+                double rz = T->z[j] - p[1];
+                double syu = poly2(g->sigma_y, p[2]);
+                kalman_update(p, C, ry, rz, r.tau, syu * syu, vz);
+                o->idx[l * n + i] = (int32_t)j;
+                nmatch++;
+                chi2sum += bchi;
+                if (o->chi2_layer) o->chi2_layer[l * n + i] = bchi;
+                if (near_lim(fabs(p[2]), g->snp_max, g->m_rel, g->m_snp)) lf |= FL_P4;
+                if (!(fabs(p[2]) < g->snp_max)) {
+                    status |= ST_STOP_SNP;
+                    flags |= lf;
+                    if (lf && flag_layer == NLAY) flag_layer = l;
+                    break;
+                }
+            }
+        }
+        flags |= lf;
+        if (lf && flag_layer == NLAY) flag_layer = l;
+        if (o->lp) {
+            double q[15];
+            pack(C, q);
+            for (int k = 0; k < 5; k++) o->lp[(l * 5 + k) * n + i] = p[k];
+            for (int k = 0; k < 15; k++) o->lc[(l * 15 + k) * n + i] = q[k];
+            o->lx[l * n + i] = x;
+            o->lsec[l * n + i] = sec;
+        }
+    }
+done:
+    pack(C, pk);
+    for (int k = 0; k < 5; k++) o->p[k * n + i] = p[k];
+    for (int k = 0; k < 15; k++) o->c[k * n + i] = pk[k];
+    o->x[i] = x;
+    o->sec[i] = sec;
+    o->chi2[i] = chi2sum;
+    o->n_match[i] = nmatch;
+    o->status[i] = status;
+    o->flags[i] = flags;
+    if (o->flag_layer) o->flag_layer[i] = flag_layer;
+    if (o->n_cand) o->n_cand[i] = ncand;
+}
+
+/* Matches every track.  mode 0: binned search over the sorted cells;
+ * mode 1: brute force over all tracklets of the same group/sector/layer. */
+int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *tc,
+                 const double *tx, const int32_t *tsec, const int32_t *tgrp,
+                 int64_t n_tkl, const double *ky, const double *kz, const double *kdy,
+                 const uint32_t *kdetrow, const int32_t *kgrp, int32_t n_groups,
+                 int32_t mode, int32_t n_threads,
+                 int32_t *idx, double *op, double *oc, double *ox, int32_t *osec,
+                 double *ochi2, double *ochi2_layer, int32_t *on_match, uint32_t *ostatus,
+                 uint32_t *oflags, int32_t *oflag_layer, int64_t *on_cand,
+                 double *lp, double *lc, double *lx, int32_t *lsec)
+{
+    otkl T = {ky, kz, kdy, kdetrow, kgrp, n_tkl, NULL, NULL, n_groups, mode == 1};
+    int32_t *perm = NULL;
+    uint32_t *offsets = NULL;
+    if (n_groups < 1) return -1;
+    if (!T.brute) {
+        int64_t nc = n_cells_of(g, n_groups);
+        perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_tkl > 0 ? n_tkl : 1));
+        offsets = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nc + 1));
+        if (!perm || !offsets) { free(perm); free(offsets); return -2; }
+        oracle_bin(g, n_tkl, ky, kz, kdy, kdetrow, kgrp, n_groups, perm, offsets);
+        T.perm = perm;
+        T.offsets = offsets;
+    }
+    double dxmax = 0.0;
+    for (int d = 0; d < NDET; d++) dxmax = fabs(g->dx_chamber[d]) > dxmax ? fabs(g->dx_chamber[d]) : dxmax;
+    oout o = {idx, op, oc, ox, osec, ochi2, ochi2_layer, on_match, ostatus, oflags, oflag_layer,
+              on_cand, lp, lc, lx, lsec};
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel
+    {
+        ilist L = {NULL, 0, 0};
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n_trk; i++)
+            match_one(g, i, n_trk, tp, tc, tx, tsec, tgrp, &T, dxmax, &o, &L);
+        free(L.v);
+    }
+    free(perm);
+    free(offsets);
+    return 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------- */
+/* single steps, exported for the unit pins                               */
+/* ---------------------------------------------------------------------- */
+
+int oracle_propagate(const ocfg *g, double *p, double *cpk, double *x, double x2, double *J)
+{
+    double C[5][5], Jm[5][5];
+    if (cpk) unpack(cpk, C);
+    int ok = propagate(p, cpk ? C : NULL, x, x2, g, NULL, Jm);
+    if (ok && cpk) pack(C, cpk);
+    if (ok && J) memcpy(J, Jm, sizeof(Jm));
+    return ok;
+}
+
+int oracle_rotate(const ocfg *g, double *p, double *cpk, double *x, double da, double *J)
+{
+    double C[5][5], Jm[5][5];
+    if (cpk) unpack(cpk, C);
+    int ok = rotate(p, cpk ? C : NULL, x, da, g, Jm);
+    if (ok && cpk) pack(C, cpk);
+    if (ok && J) memcpy(J, Jm, sizeof(Jm));
+    return ok;
+}
+
+void oracle_add_ms(const ocfg *g, const double *p, double *cpk)
+{
+    double C[5][5];
+    unpack(cpk, C);
+    add_ms(p, C, g);
+    pack(C, cpk);
+}
+
+void oracle_update(double *p, double *cpk, double ry, double rz, double tau, double vy, double vz)
+{
+    double C[5][5];
+    unpack(cpk, C);
+    kalman_update(p, C, ry, rz, tau, vy, vz);
+    pack(C, cpk);
+}
+
+int oracle_ldl_pd(const double *cpk)
+{
+    double C[5][5];
+    unpack(cpk, C);
+    return ldl_pd(C);
+}
+
+int64_t oracle_key(const ocfg *g, double y, double z, double dy, uint32_t det_row, int32_t grp,
+                   int32_t n_groups)
+{
+    return tkl_key(g, y, z, dy, det_row, grp, n_groups);
+}
+
+int32_t oracle_cfg_size(void) { return (int32_t)sizeof(ocfg); }

@@ -1,0 +1,228 @@
+"""Pins of the oracle's search, binning and filter statistics.
+
+Binning against numpy's stable sort, binned search against brute force over
+all tracklets of the sector/layer, invariance under bin width and input order,
+chi2 and pull statistics of the filter on simulated tracks, noise-free chi2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2003_03174_amd import synth
+
+
+def _wl(n, seed, **kw):
+    params = kw.pop("params", {})
+    return synth.generate(n_tracks=n, seed=seed, params=params, **kw)
+
+
+def test_binning_is_stable_sort_of_keys():
+    w = _wl(300, 1, fake_ratio=1.0)
+    P = w["params"]
+    perm, off = O.bin_tracklets(P, w)
+    n = w["n_tracklets"]
+    keys = np.array([O.key(P, w["tkl_y"][i], w["tkl_z"][i], w["tkl_dy"][i], int(w["tkl_det_row"][i]))
+                     for i in range(n)])
+    ref = np.argsort(keys, kind="stable")
+    assert np.array_equal(perm, ref)
+    nc = 540 * 18 * P["n_yb"]
+    assert off[nc] == n and np.all(np.diff(off.astype(np.int64)) >= 0)
+    counts = np.bincount(keys, minlength=nc + 1)[:nc]
+    assert np.array_equal(np.diff(off.astype(np.int64)), counts)
+
+
+def test_bin_key_geometry():
+    """Each key decodes to the tracklet's own det/row, and its y lies in the
+    bin's interval unless clamped at the ends."""
+    w = _wl(300, 2, fake_ratio=1.0)
+    P = w["params"]
+    wb, nyb = P["y_bin_w"], P["n_yb"]
+    ymin = -wb * nyb / 2
+    for i in range(0, w["n_tracklets"], 7):
+        k = O.key(P, w["tkl_y"][i], w["tkl_z"][i], w["tkl_dy"][i], int(w["tkl_det_row"][i]))
+        yb = k % nyb
+        row = (k // nyb) % 18
+        det = k // (nyb * 18)
+        assert det == w["tkl_det"][i] and row == w["tkl_row"][i]
+        y = w["tkl_y"][i]
+        lo, hi = ymin + yb * wb, ymin + (yb + 1) * wb
+        assert (lo <= y < hi) or (yb == 0 and y < lo) or (yb == nyb - 1 and y >= hi)
+
+
+def test_invalid_tracklets_go_last():
+    w = _wl(50, 3)
+    P = w["params"]
+    w["tkl_det_row"] = w["tkl_det_row"].copy()
+    w["tkl_y"] = w["tkl_y"].copy()
+    w["tkl_det_row"][0] = (600 << 5) | 3   # det out of range
+    w["tkl_y"][1] = np.nan
+    perm, off = O.bin_tracklets(P, w)
+    n = w["n_tracklets"]
+    nc = 540 * 18 * P["n_yb"]
+    assert off[nc] == n - 2
+    assert set(perm[n - 2:]) == {0, 1}
+
+
+@pytest.mark.parametrize("tilt", [False, True])
+def test_binned_equals_brute_force(tilt):
+    """Identical indices, chi2, states and flags on tiny dense inputs."""
+    n_seeds = 60
+    for seed in range(n_seeds):
+        params = dict(y_bin_w=4.0, n_yb=32)
+        if tilt:
+            params["tilt"] = synth.tilt_pm2deg()
+            rng = np.random.default_rng(seed)
+            params["dx_chamber"] = rng.uniform(-0.5, 0.5, 540)
+        w = _wl(20, 1000 + seed, fake_ratio=20.0, params=params)
+        P = w["params"]
+        a = O.match(P, w, mode="binned", threads=1)
+        b = O.match(P, w, mode="brute", threads=1)
+        for k in ("idx", "chi2", "p", "cov", "x", "sector", "status", "flags", "n_match"):
+            assert np.array_equal(a[k], b[k]), (seed, k)
+
+
+def test_independent_of_bin_width_and_order():
+    base = _wl(200, 77, fake_ratio=3.0, params=dict(y_bin_w=8.0, n_yb=16))
+    ref = O.match(base["params"], base, threads=2)
+    for wb, nyb in ((1.0, 128), (2.0, 64), (4.0, 32), (16.0, 8)):
+        P = synth.default_params(y_bin_w=wb, n_yb=nyb)
+        o = O.match(P, base, threads=2)
+        assert np.array_equal(o["idx"], ref["idx"])
+        assert np.array_equal(o["p"], ref["p"])
+    # permuting the input tracklets only relabels the result
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(base["n_tracklets"])
+    w2 = dict(base)
+    for k in ("tkl_y", "tkl_z", "tkl_dy", "tkl_det_row", "tkl_group"):
+        w2[k] = base[k][perm]
+    o2 = O.match(base["params"], w2, threads=2)
+    mapped = np.where(o2["idx"] >= 0, perm[np.maximum(o2["idx"], 0)], -1)
+    assert np.array_equal(mapped, ref["idx"])
+    assert np.array_equal(o2["p"], ref["p"])
+
+
+def test_noise_free_chi2_vanishes():
+    P = synth.default_params()
+    rng = np.random.default_rng(12)
+    g = synth.generate_group(rng, P, 300, noise_free=True, fake_ratio=0.5, fp32=False)
+    w = synth._concat_groups([g], P)
+    o = O.match(P, w, threads=2)
+    m = o["idx"] >= 0
+    assert m.sum() > 1500
+    assert np.all(o["idx"][m] == w["true_idx"][m])
+    assert o["chi2_layer"][m].max() < 1e-18
+
+
+@pytest.mark.parametrize("variant", ["plain", "tilt_dx"])
+def test_chi2_mean_is_ndf(variant):
+    """True matches, no fakes, no chi2 cut: E[chi2] = 2 (two measured
+    coordinates), within 3 standard errors (Var = 4 for 2 dof)."""
+    params = dict(chi2_max=1e9, n_sigma_road=40.0)
+    if variant == "tilt_dx":
+        params["tilt"] = synth.tilt_pm2deg()
+        params["dx_chamber"] = np.random.default_rng(2).uniform(-0.5, 0.5, 540)
+    w = _wl(3000, 31, fake_ratio=0.0, params=params)
+    o = O.match(w["params"], w, threads=4)
+    m = (o["idx"] >= 0) & (o["idx"] == w["true_idx"])
+    c2 = o["chi2_layer"][m]
+    N = c2.size
+    assert N > 15000
+    assert abs(c2.mean() - 2.0) < 3 * math.sqrt(4.0 / N), c2.mean()
+
+
+def test_pulls_unit_width():
+    """(estimate - truth)/sigma at every layer: mean 0 and RMS 1."""
+    params = dict(chi2_max=1e9, n_sigma_road=40.0)
+    w = _wl(6000, 41, fake_ratio=0.0, params=params)
+    o = O.match(w["params"], w, threads=4, layers=True)
+    T = w["truth"]
+    names = ("y", "z", "snp", "tgl", "qpt")
+    diag = (0, 5, 9, 12, 14)
+    for l in (1, 3, 5):
+        ok = (o["lsec"][l] == T["sec"][l]) & (o["idx"][l] == w["true_idx"][l]) & (w["true_idx"][l] >= 0)
+        ok &= o["status"] == 0
+        N = ok.sum()
+        assert N > 4000
+        for k in range(5):
+            pull = (o["lp"][l, k, ok] - T[names[k]][l, ok]) / np.sqrt(o["lc"][l, diag[k], ok])
+            assert abs(pull.mean()) < 4.0 / math.sqrt(N), (l, names[k], pull.mean())
+            assert abs(pull.std() - 1.0) < 0.05, (l, names[k], pull.std())
+
+
+def test_covariance_spd_everywhere():
+    w = _wl(2000, 51, fake_ratio=0.5)
+    o = O.match(w["params"], w, threads=4, layers=True)
+    for i in range(0, w["n_tracks"], 3):
+        assert O.ldl_pd(o["cov"][:, i])
+        for l in range(6):
+            if np.isfinite(o["lx"][l, i]):
+                assert O.ldl_pd(o["lc"][l, :, i])
+
+
+def test_tracks_below_reach_stop():
+    """Helices from the vertex that reach r = 250 cm but have 2R < 290 cm
+    (pT below 0.2173 GeV/c at 0.5 T) never reach the first layer: the oracle
+    stops them with no match, whatever their direction."""
+    P = synth.default_params(snp_max=0.999999)
+    rng = np.random.default_rng(61)
+    n = 500
+    pt = rng.uniform(0.19, 0.2170, n)
+    q = rng.choice([-1.0, 1.0], n)
+    phi0 = rng.random(n) * 2 * np.pi
+    cu = -synth.KAPPA * 0.5 * q / pt
+    ok, phi_pos, phi_dir, arc = synth._cross_cylinder(phi0, cu, 250.0, np.float64)
+    assert ok.all()
+    X, Y = 250 * np.cos(phi_pos), 250 * np.sin(phi_pos)
+    sec = synth._sector_of(X, Y)
+    a = synth._alpha(sec, np.float64)
+    w = _wl(10, 1)
+    w["p"] = np.stack([-X * np.sin(a) + Y * np.cos(a), 0.3 * arc, np.sin(phi_dir - a),
+                       np.full(n, 0.3), q / pt])
+    w["cov"] = np.tile(w["cov"][:, :1], (1, n))
+    w["x"] = X * np.cos(a) + Y * np.sin(a)
+    w["sector"] = sec.astype(np.int32)
+    w["group"] = np.zeros(n, np.int32)
+    o = O.match(P, w, threads=4)
+    assert np.all(o["n_match"] == 0)
+    assert np.all(o["status"] & (O.ST_STOP_SNP | O.ST_ROT_FAIL))
+    assert np.all(np.isnan(o["chi2_layer"]) | (o["chi2_layer"] == 0))
+
+
+def test_purity_without_fakes():
+    """Sanity only (the paper's efficiency/purity curves are not reproduced):
+    no fakes means every attached tracklet belongs to the track."""
+    w = _wl(3000, 71, fake_ratio=0.0)
+    o = O.match(w["params"], w, threads=4)
+    att = o["n_match"] >= 2
+    clean = np.all((o["idx"] < 0) | (o["idx"] == w["true_idx"]), axis=0)
+    assert (clean & att).sum() / att.sum() >= 0.99
+
+
+def test_groups_are_isolated():
+    """A track only sees tracklets of its own group (frame)."""
+    P = synth.default_params()
+    w = synth.generate(n_tracks=300, seed=5, groups=3, fake_ratio=0.5)
+    o = O.match(P, w, threads=2)
+    m = o["idx"] >= 0
+    tg = w["tkl_group"][o["idx"][m]]
+    trg = np.broadcast_to(w["group"], o["idx"].shape)[m]
+    assert np.array_equal(tg, trg)
+    # the same frame alone gives the same answer
+    sel = w["group"] == 1
+    w1 = synth.generate(n_tracks=300, seed=5, groups=3, fake_ratio=0.5)
+    keep = w1["tkl_group"] == 1
+    w1b = dict(w1)
+    for k in ("tkl_y", "tkl_z", "tkl_dy", "tkl_det_row"):
+        w1b[k] = w1[k][keep]
+    w1b["tkl_group"] = np.zeros(keep.sum(), np.int32)
+    w1b["n_groups"] = 1
+    for k in ("p", "cov"):
+        w1b[k] = np.ascontiguousarray(w1[k][:, sel])
+    w1b["x"], w1b["sector"] = w1["x"][sel], w1["sector"][sel]
+    w1b["group"] = np.zeros(sel.sum(), np.int32)
+    o1 = O.match(P, w1b, threads=2)
+    base = np.nonzero(keep)[0]
+    mapped = np.where(o1["idx"] >= 0, base[np.maximum(o1["idx"], 0)], -1)
+    assert np.array_equal(mapped, o["idx"][:, sel])
