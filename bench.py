@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the TRD matching hot path on one MI355X.
+
+One step = bin all tracklets of the batch (keys + histogram, scan, stable
+scatter) and match every seed track through the six layers, with the inputs
+already resident in device memory.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def match_alg_bytes(n_trk, n_tkl, n_cells, prec):
+    """Algorithmic bytes of one match launch: track state in and out, each
+    binned tracklet record once, the cell offsets once."""
+    f = 8 if prec == "fp64" else 4
+    trk_in = 21 * f + 4 + 4                 # p, cov, x; sector, group
+    trk_out = 21 * f + f + 6 * 4 + 3 * 4    # p, cov, x; chi2; idx; sector, n_match, status
+    return n_trk * (trk_in + trk_out) + n_tkl * 16 + (n_cells + 1) * 4
+
+
+def bin_alg_bytes(n_tkl, n_cells):
+    """Algorithmic bytes of the binning: read y, z, dy, det_row, group (20 B)
+    twice (histogram, scatter), write the 16 B record, count/offset traffic."""
+    return n_tkl * (20 + 20 + 16) + n_cells * 16
+
+
+def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0):
+    import torch
+    from paper_2003_03174_amd import binding as B
+    from paper_2003_03174_amd import synth
+
+    lay = synth.to_device_layout(w)
+    d = B.device_inputs(lay, prec)
+    n = w["n_tracks"]
+    m = B.Matcher(w["params"], prec, block_size=block_size, search_lanes=search_lanes)
+    m.reserve(w["n_tracklets"], w["n_groups"], n)
+    out = m.alloc_results(n, chi2_layer=False)
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        if evs:
+            evs[0].record(stream)
+        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+        if evs:
+            evs[1].record(stream)
+        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+        if evs:
+            evs[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_bin = [e[0].elapsed_time(e[1]) for e in evs]
+    t_match = [e[1].elapsed_time(e[2]) for e in evs]
+    t_step = [e[0].elapsed_time(e[2]) for e in evs]
+    st = out["status"].cpu().numpy()
+    nm = out["n_match"].cpu().numpy()
+    res = dict(wall_ms_per_step=1e3 * wall / steps, bin_ms=t_bin, match_ms=t_match, step_ms=t_step,
+               n_fallback=int(((st & B.TRK_FP64_FALLBACK) != 0).sum()),
+               n_ge2=int((nm >= 2).sum()))
+    m.close()
+    return res
+
+
+def pct(v, q):
+    v = sorted(v)
+    k = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The FP64 oracle on the host cores: binning of all tracklets plus the
+    matching of a bounded sample of tracks, extrapolated to the batch."""
+    import numpy as np
+    from oracle import oracle as O
+
+    P = w["params"]
+    n = w["n_tracks"]
+    t0 = time.perf_counter()
+    O.bin_tracklets(P, w)
+    t_bin = time.perf_counter() - t0
+    probe = np.arange(0, n, max(1, n // 2000))
+    t0 = time.perf_counter()
+    O.match(P, w, threads=0, track_slice=probe)
+    t_probe = max(time.perf_counter() - t0 - t_bin, 1e-6) / probe.size
+    ns = int(min(n, max(probe.size, budget_s / t_probe)))
+    sample = np.arange(0, n, max(1, n // ns))[:ns]
+    t0 = time.perf_counter()
+    O.match(P, w, threads=0, track_slice=sample)
+    t_call = time.perf_counter() - t0
+    per_trk = max(t_call - t_bin, 1e-9) / sample.size
+    est = t_bin + per_trk * n
+    return dict(value=n / est, unit="tracks/s", cores=int(O.lib().oracle_max_threads()), kind="oracle",
+                sample=(f"binning of all {w['n_tracklets']} tracklets ({t_bin:.2f} s) + matching of "
+                        f"{sample.size} of {n} tracks (every {max(1, n // ns)}th, {t_call - t_bin:.2f} s), "
+                        f"extrapolated to the whole batch"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c5_distortion_450k")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_cov64", "fp64"])
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--search-lanes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 512 MiB device-to-device copy first (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the path shards by "
+                                   "frame with no exchange (see DESIGN.md), multi-GPU runs are "
+                                   "not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2003_03174_amd import synth
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+
+    if args.calibrate_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 512 MiB read + 512 MiB written")
+        del src, dst
+    log(f"generating {args.workload}")
+    w = synth.generate(args.workload)
+    P = w["params"]
+    n, ntk, ng = w["n_tracks"], w["n_tracklets"], w["n_groups"]
+    n_cells = ng * 540 * P["n_rows"] * P["n_yb"]
+    log(f"{n} tracks, {ntk} tracklets, {n_cells} cells; timing {args.precision}")
+    r = run_gpu(w, args.precision, args.steps, args.warmup, args.block_size, args.search_lanes)
+    ms = r["wall_ms_per_step"]
+    match_avg = sum(r["match_ms"]) / len(r["match_ms"])
+    bin_avg = sum(r["bin_ms"]) / len(r["bin_ms"])
+    log(f"{ms:.3f} ms/step (bin {bin_avg:.3f} ms, match {match_avg:.3f} ms)")
+    ab = match_alg_bytes(n, ntk, n_cells, args.precision)
+    achieved = ab / (match_avg * 1e-3) / 1e9
+    line = {
+        "metric": "matched tracks/s (6-layer Kalman)",
+        "value": n / (ms * 1e-3),
+        "unit": "tracks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: {n} seed tracks, {ntk} tracklets (50% fakes), "
+                         f"pT^-3 above 0.3 GeV/c, 5-15 cm seed distortion, road 3 sigma, "
+                         f"{n_cells} cells (2 cm y bins)"),
+            "precision": args.precision,
+            "block_size": args.block_size or 256,
+            "search_lanes": args.search_lanes or 8,
+            "step": "bin all tracklets + match all tracks",
+        },
+        "latency_ms": {"step_p50": pct(r["step_ms"], 50), "step_p99": pct(r["step_ms"], 99),
+                       "bin_avg": bin_avg, "match_avg": match_avg},
+        "tracks_ge2_matches_per_s": r["n_ge2"] / (ms * 1e-3),
+        "fp64_fallback_tracks": r["n_fallback"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_match (trd_match)", "alg_bytes_per_launch": ab},
+    }
+    if not args.no_fp64 and args.precision != "fp64":
+        log("timing the plain FP64 comparator")
+        r64 = run_gpu(w, "fp64", max(3, args.steps // 2), 2)
+        line["fp64_plain"] = {"value": n / (r64["wall_ms_per_step"] * 1e-3), "unit": "tracks/s",
+                              "ms_per_step": r64["wall_ms_per_step"],
+                              "match_avg_ms": sum(r64["match_ms"]) / len(r64["match_ms"])}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * trd.h -- C ABI of the MI355X TRD tracklet-to-track matcher.
+ *
+ * Problem (paper, abstract and Sect. 3): given ITS-TPC seed tracks
+ * extrapolated to the TRD and the TRD tracklets of the same interaction(s),
+ * return for every track the tracklet matched in each of the six layers (at
+ * most one per layer) and the track state after the Kalman updates.  Tracks
+ * are independent; a track only sees tracklets of its own group (frame or
+ * trigger, Sect. 4 of the paper).
+ *
+ * Conventions
+ *   - Units: cm, GeV/c, tesla.  Track state p = (y, z, sin phi, tan lambda,
+ *     q/pT) at local x in the frame of sector `sector`, rotated by
+ *     alpha = (sector + 1/2) * 20 degrees.  Covariance: upper triangle of the
+ *     symmetric 5x5 matrix, row-major, 15 values.
+ *   - All array arguments are DEVICE pointers in structure-of-arrays layout,
+ *     component-major: element k of track i is at [k * n + i].
+ *   - Floating-point arrays of tracks and results are float (TRD_PREC_FP32,
+ *     TRD_PREC_FP32_COV64) or double (TRD_PREC_FP64), as set in the config.
+ *   - Every call enqueues work on `hip_stream` (a hipStream_t, NULL = default
+ *     stream) and returns without waiting.  The caller synchronises.  One
+ *     context must not be used from two streams at once; contexts are
+ *     independent of each other.
+ *   - Calls return an int status (TRD_OK or a negative TRD_E* code) and never
+ *     throw across the ABI.  Invalid arguments are reported synchronously
+ *     (TRD_EINVAL).  A HIP error raised by enqueued work is reported as
+ *     TRD_EDEVICE by the next call on the context.  Per-track problems never
+ *     fail a call: they are status bits (TRD_TRK_*).
+ */
+#ifndef TRD_H
+#define TRD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRD_N_SECTORS 18
+#define TRD_N_STACKS 5
+#define TRD_N_LAYERS 6
+#define TRD_N_DET 540 /* sector * 30 + stack * 6 + layer */
+
+/* call status */
+#define TRD_OK 0
+#define TRD_EINVAL (-1)  /* bad config, shape or pointer */
+#define TRD_ENOMEM (-2)  /* device allocation failed */
+#define TRD_EDEVICE (-3) /* HIP error from enqueued work or the runtime */
+#define TRD_ESTATE (-4)  /* trd_match before any trd_load_tracklets */
+#define TRD_EBUDGET (-5) /* request exceeds the context's HBM budget */
+
+/* arithmetic of the match kernel */
+#define TRD_PREC_FP64 0       /* everything in double */
+#define TRD_PREC_FP32 1       /* float state and covariance; tracks whose
+                                 covariance stops being positive definite
+                                 are re-run with a double covariance */
+#define TRD_PREC_FP32_COV64 2 /* float state, double covariance */
+
+/* per-track status bits (trd_results.status) */
+#define TRD_TRK_STOP_SNP 1u      /* |sin phi| reached snp_max: track stopped */
+#define TRD_TRK_ROT_FAIL 2u      /* sector change impossible: track stopped */
+#define TRD_TRK_OUT_OF_Z 4u      /* a layer's search window missed the chambers in z */
+#define TRD_TRK_FP64_FALLBACK 8u /* result comes from the double-covariance re-run */
+#define TRD_TRK_NOT_PD 16u       /* float covariance lost positive definiteness */
+#define TRD_TRK_BAD_INPUT 32u    /* non-finite seed, bad sector/group, |snp| >= snp_max,
+                                    or covariance not positive definite; copied through */
+
+/* config flags */
+#define TRD_CFG_FAIL_ALLOC 1u     /* test hook: trd_create fails with TRD_ENOMEM */
+#define TRD_CFG_FORCE_FALLBACK 2u /* test hook (TRD_PREC_FP32): every track takes the
+                                     double-covariance re-run */
+
+typedef struct trd_ctx trd_ctx;
+
+/* Plain-value configuration.  Geometry and resolutions follow Sect. 3 of the
+ * paper (18 sectors x 5 stacks x 6 layers, tracklets with y, dy over the drift
+ * length and a pad row, tilted pads); the numbers the paper leaves open are
+ * fields. */
+typedef struct trd_config {
+    uint32_t struct_size;     /* sizeof(trd_config) */
+    int32_t precision;        /* TRD_PREC_* */
+    double x_layer[6];        /* radius (local x) of each layer's chamber plane */
+    double tilt[6];           /* tan(pad tilt) per layer; y measured = y + tilt*(z - z_row) */
+    double z_min;             /* lower z edge of stack 0; chambers span [z_min, -z_min] */
+    double pad_len;           /* pad-row length in z */
+    int32_t n_rows;           /* pad rows per stack (<= 32) */
+    int32_t n_yb;             /* y bins per pad row in the tracklet cells */
+    double y_bin_w;           /* y bin width, a power of two; bins cover
+                                 [-n_yb*w/2, n_yb*w/2), outer bins are open */
+    double drift_len;         /* drift length L: dy = L * (tan phi - tan_psi) */
+    double dx_chamber[540];   /* radial offset of each chamber from x_layer (misalignment) */
+    double bz;                /* solenoid field */
+    double x_over_x0;         /* material per layer, radiation lengths */
+    double mass;              /* particle mass for scattering */
+    double sigma_y[3];        /* y resolution a0 + a1 s + a2 s^2, s = sin phi */
+    double sigma_dy[3];       /* dy resolution, same polynomial form */
+    double tan_psi;           /* tangent of the Lorentz angle */
+    double chi2_max;          /* chi2 cut of a candidate (2 dof) */
+    double n_sigma_dy;        /* dy exclusion gate, in sigma (paper: 4) */
+    double n_sigma_road;      /* road half widths n * sqrt(S_yy), n * sqrt(S_zz) */
+    double snp_max;           /* stop when |sin phi| reaches this */
+    uint64_t hbm_budget_bytes;/* cap on the context's device memory, 0 = none */
+    int32_t block_size;       /* match workgroup size: 64, 128, 192 or 256; 0 = 256 */
+    int32_t search_lanes;     /* float paths: lanes that scan one track's road together:
+                                 1 (one lane per track), 4, 8, 16, 32 or 64; 0 = 8 */
+    uint32_t flags;           /* TRD_CFG_* */
+    uint32_t reserved;        /* must be 0 */
+} trd_config;
+
+/* Tracklets of one or more groups (device arrays of length n). */
+typedef struct trd_tracklets {
+    const float *y;          /* offset at the chamber radius */
+    const float *z;          /* pad-row centre */
+    const float *dy;         /* deflection over the drift length */
+    const uint32_t *det_row; /* (det << 5) | pad row within the stack */
+    const int32_t *group;    /* group id in [0, n_groups), or NULL: all 0 */
+} trd_tracklets;
+
+/* Seed tracks (device arrays, float or double per precision). */
+typedef struct trd_tracks {
+    const void *p;         /* [5][n] */
+    const void *cov;       /* [15][n] */
+    const void *x;         /* [n] local x of the state */
+    const int32_t *sector; /* [n] */
+    const int32_t *group;  /* [n] or NULL: all 0 */
+} trd_tracks;
+
+/* Results (device arrays allocated by the caller). */
+typedef struct trd_results {
+    int32_t *idx;      /* [6][n] input-order tracklet index per layer, -1 if none */
+    void *p;           /* [5][n] state after the last layer reached */
+    void *cov;         /* [15][n] */
+    void *x;           /* [n] */
+    int32_t *sector;   /* [n] sector frame of the output state */
+    void *chi2;        /* [n] sum of the matched candidates' chi2 */
+    void *chi2_layer;  /* [6][n] chi2 per layer (0 if none), or NULL */
+    int32_t *n_match;  /* [n] number of matched layers */
+    uint32_t *status;  /* [n] TRD_TRK_* bits */
+} trd_results;
+
+/* Read-only view of the context's sorted tracklets. */
+typedef struct trd_binning_view {
+    const uint32_t *offsets; /* [n_cells + 1]: first sorted position of each cell;
+                                offsets[n_cells] = number of valid tracklets */
+    const float *sorted;     /* [n_valid][4]: y, dy, z, input index (int32 bits),
+                                ordered by (cell, input index) */
+    int64_t n_cells;         /* n_groups * 540 * n_rows * n_yb */
+    int64_t n_tracklets;     /* tracklets passed to the last load */
+} trd_binning_view;
+
+/* Validates the config, selects `device` and uploads the geometry.
+ * Errors: TRD_EINVAL (bad config), TRD_ENOMEM, TRD_EDEVICE.  On success *out
+ * owns the context until trd_destroy. */
+int trd_create(const trd_config *cfg, int device, trd_ctx **out);
+
+/* Reserves device buffers for up to `max_tracklets` tracklets, `max_groups`
+ * groups and `max_tracks` tracks, so that later loads and matches of that
+ * size allocate nothing (needed under stream capture).  Synchronous.
+ * Errors: TRD_EINVAL, TRD_ENOMEM, TRD_EBUDGET. */
+int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t max_tracks);
+
+/* Bins the tracklets into (group, chamber, pad row, y bin) cells: exact
+ * cell keys, counts, exclusive scan and a stable scatter into ctx-owned
+ * sorted storage.  The caller may reuse `t`'s buffers once the stream has
+ * passed this call.  Tracklets with a det >= 540, a row >= n_rows, a group
+ * outside [0, n_groups) or a non-finite value are dropped.
+ * Errors: TRD_EINVAL (n < 0, n_groups < 1, NULL pointers with n > 0,
+ * too many cells), TRD_ENOMEM, TRD_EBUDGET, TRD_EDEVICE. */
+int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t n_groups,
+                       void *hip_stream);
+
+/* Matches n tracks against the tracklets of the last load (Sect. 3 of the
+ * paper: propagation to each layer, sector rotation, multiple scattering,
+ * covariance road, dy exclusion, chi2 from y and z, best candidate, precise
+ * propagation and Kalman update).  Errors: TRD_EINVAL, TRD_ESTATE,
+ * TRD_ENOMEM, TRD_EBUDGET, TRD_EDEVICE. */
+int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream);
+
+/* Fills *out with the context's sorted tracklets (valid until the next load
+ * or destroy; read them on the load's stream).  Errors: TRD_EINVAL, TRD_ESTATE. */
+int trd_get_binning(trd_ctx *ctx, trd_binning_view *out);
+
+/* Copies the context's sorted tracklets into caller device buffers:
+ * offsets_out[n_cells + 1] and sorted_out[4 * n_valid] (layout as in
+ * trd_binning_view), stream-ordered after the last load.  n_valid is
+ * offsets[n_cells]; pass capacity max_valid >= it (use n_tracklets).
+ * Errors: TRD_EINVAL, TRD_ESTATE, TRD_EDEVICE. */
+int trd_copy_binning(trd_ctx *ctx, uint32_t *offsets_out, float *sorted_out, int64_t max_valid,
+                     void *hip_stream);
+
+/* Device memory currently held by the context, in bytes. */
+int64_t trd_device_bytes(const trd_ctx *ctx);
+
+/* Frees everything the context owns.  Waits for its device work. NULL is a no-op. */
+void trd_destroy(trd_ctx *ctx);
+
+/* Static text for a call status code. */
+const char *trd_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRD_H */

@@ -1,0 +1,298 @@
+"""Python binding of libtrd (include/trd.h): argument marshalling only.
+
+Every step of the matching runs in the HIP kernels of libtrd.so; this module
+packs plain parameters into `trd_config`, hands torch device tensors to the C
+ABI as raw pointers and raises on error codes.  Torch provides device memory
+and streams, nothing else.  There is no CPU fallback: without the built
+library (or a GPU) every call fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrd.so")
+
+TRD_OK, TRD_EINVAL, TRD_ENOMEM, TRD_EDEVICE, TRD_ESTATE, TRD_EBUDGET = 0, -1, -2, -3, -4, -5
+TRD_PREC_FP64, TRD_PREC_FP32, TRD_PREC_FP32_COV64 = 0, 1, 2
+PRECISIONS = {"fp64": TRD_PREC_FP64, "fp32": TRD_PREC_FP32, "fp32_cov64": TRD_PREC_FP32_COV64}
+TRK_STOP_SNP, TRK_ROT_FAIL, TRK_OUT_OF_Z, TRK_FP64_FALLBACK, TRK_NOT_PD, TRK_BAD_INPUT = 1, 2, 4, 8, 16, 32
+TRD_CFG_FAIL_ALLOC = 1
+TRD_CFG_FORCE_FALLBACK = 2
+
+# every symbol include/trd.h declares
+EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_get_binning",
+           "trd_copy_binning", "trd_device_bytes", "trd_destroy", "trd_status_string")
+
+
+class TrdError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {trd_status_string(code)} ({code})")
+        self.code = code
+
+
+class trd_config(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("precision", C.c_int32),
+        ("x_layer", C.c_double * 6), ("tilt", C.c_double * 6),
+        ("z_min", C.c_double), ("pad_len", C.c_double),
+        ("n_rows", C.c_int32), ("n_yb", C.c_int32),
+        ("y_bin_w", C.c_double), ("drift_len", C.c_double),
+        ("dx_chamber", C.c_double * 540),
+        ("bz", C.c_double), ("x_over_x0", C.c_double), ("mass", C.c_double),
+        ("sigma_y", C.c_double * 3), ("sigma_dy", C.c_double * 3), ("tan_psi", C.c_double),
+        ("chi2_max", C.c_double), ("n_sigma_dy", C.c_double), ("n_sigma_road", C.c_double),
+        ("snp_max", C.c_double),
+        ("hbm_budget_bytes", C.c_uint64), ("block_size", C.c_int32), ("search_lanes", C.c_int32),
+        ("flags", C.c_uint32), ("reserved", C.c_uint32),
+    ]
+
+
+class trd_tracklets(C.Structure):
+    _fields_ = [("y", C.c_void_p), ("z", C.c_void_p), ("dy", C.c_void_p),
+                ("det_row", C.c_void_p), ("group", C.c_void_p)]
+
+
+class trd_tracks(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("cov", C.c_void_p), ("x", C.c_void_p),
+                ("sector", C.c_void_p), ("group", C.c_void_p)]
+
+
+class trd_results(C.Structure):
+    _fields_ = [("idx", C.c_void_p), ("p", C.c_void_p), ("cov", C.c_void_p), ("x", C.c_void_p),
+                ("sector", C.c_void_p), ("chi2", C.c_void_p), ("chi2_layer", C.c_void_p),
+                ("n_match", C.c_void_p), ("status", C.c_void_p)]
+
+
+class trd_binning_view(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("sorted", C.c_void_p),
+                ("n_cells", C.c_int64), ("n_tracklets", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtrd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.trd_create.argtypes = [C.POINTER(trd_config), C.c_int, C.POINTER(vp)]
+        L.trd_reserve.argtypes = [vp, C.c_int64, C.c_int32, C.c_int64]
+        L.trd_load_tracklets.argtypes = [vp, C.POINTER(trd_tracklets), C.c_int64, C.c_int32, vp]
+        L.trd_match.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
+        L.trd_get_binning.argtypes = [vp, C.POINTER(trd_binning_view)]
+        L.trd_copy_binning.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.trd_device_bytes.argtypes = [vp]
+        L.trd_device_bytes.restype = C.c_int64
+        L.trd_destroy.argtypes = [vp]
+        L.trd_destroy.restype = None
+        L.trd_status_string.argtypes = [C.c_int]
+        L.trd_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def trd_status_string(code: int) -> str:
+    return lib().trd_status_string(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != TRD_OK:
+        raise TrdError(rc, what)
+
+
+def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, search_lanes=0, flags=0):
+    """trd_config from the plain parameter dict of a workload."""
+    c = trd_config()
+    c.struct_size = C.sizeof(trd_config)
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for l in range(6):
+        c.x_layer[l] = float(params["x_layer"][l])
+        c.tilt[l] = float(params["tilt"][l])
+    c.z_min, c.pad_len = float(params["z_min"]), float(params["pad_len"])
+    c.n_rows, c.n_yb = int(params["n_rows"]), int(params["n_yb"])
+    c.y_bin_w, c.drift_len = float(params["y_bin_w"]), float(params["drift_len"])
+    for d in range(540):
+        c.dx_chamber[d] = float(params["dx_chamber"][d])
+    c.bz, c.x_over_x0, c.mass = float(params["bz"]), float(params["x_over_x0"]), float(params["mass"])
+    for k in range(3):
+        c.sigma_y[k] = float(params["sigma_y"][k])
+        c.sigma_dy[k] = float(params["sigma_dy"][k])
+    c.tan_psi = float(params["tan_psi"])
+    c.chi2_max, c.n_sigma_dy = float(params["chi2_max"]), float(params["n_sigma_dy"])
+    c.n_sigma_road, c.snp_max = float(params["n_sigma_road"]), float(params["snp_max"])
+    c.hbm_budget_bytes = int(budget_bytes)
+    c.block_size = int(block_size)
+    c.search_lanes = int(search_lanes)
+    c.flags = int(flags)
+    return c
+
+
+# ---- C-ABI calls under their own names ------------------------------------
+
+def trd_create(cfg: trd_config, device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(lib().trd_create(C.byref(cfg), int(device), C.byref(h)), "trd_create")
+    return h.value
+
+
+def trd_reserve(ctx, max_tracklets, max_groups, max_tracks):
+    _check(lib().trd_reserve(ctx, int(max_tracklets), int(max_groups), int(max_tracks)), "trd_reserve")
+
+
+def trd_load_tracklets(ctx, t: trd_tracklets, n, n_groups, stream=0):
+    _check(lib().trd_load_tracklets(ctx, C.byref(t), int(n), int(n_groups), stream or None),
+           "trd_load_tracklets")
+
+
+def trd_match(ctx, trk: trd_tracks, n, res: trd_results, stream=0):
+    _check(lib().trd_match(ctx, C.byref(trk), int(n), C.byref(res), stream or None), "trd_match")
+
+
+def trd_get_binning(ctx) -> trd_binning_view:
+    v = trd_binning_view()
+    _check(lib().trd_get_binning(ctx, C.byref(v)), "trd_get_binning")
+    return v
+
+
+def trd_copy_binning(ctx, offsets_ptr, sorted_ptr, max_valid, stream=0):
+    _check(lib().trd_copy_binning(ctx, offsets_ptr, sorted_ptr, int(max_valid), stream or None),
+           "trd_copy_binning")
+
+
+def trd_device_bytes(ctx) -> int:
+    return int(lib().trd_device_bytes(ctx))
+
+
+def trd_destroy(ctx):
+    if ctx:
+        lib().trd_destroy(ctx)
+
+
+# ---- torch-facing convenience ------------------------------------------------
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Matcher:
+    """One context: tracklets stay resident on the device between matches.
+
+    Tensors passed in must be contiguous device tensors in the layouts of
+    include/trd.h (component-major [k][n] for p and cov).
+    """
+
+    def __init__(self, params, precision="fp32", device=0, budget_bytes=0, block_size=0,
+                 search_lanes=0, flags=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the TRD matcher needs a HIP device")
+        self.params = params
+        self.precision = precision
+        self.device = device
+        self.cfg = make_config(params, precision, budget_bytes=budget_bytes, block_size=block_size,
+                               search_lanes=search_lanes, flags=flags)
+        self.ctx = trd_create(self.cfg, device)
+        self.fdtype = torch.float64 if precision == "fp64" else torch.float32
+        self.n_tracklets = 0
+        self.n_groups = 1
+
+    def close(self):
+        if self.ctx:
+            trd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, max_tracklets, max_groups, max_tracks):
+        trd_reserve(self.ctx, max_tracklets, max_groups, max_tracks)
+
+    def load(self, y, z, dy, det_row, group=None, n_groups=1, stream=None):
+        self._keep_in = (y, z, dy, det_row, group)
+        for t in (y, z, dy, det_row) + ((group,) if group is not None else ()):
+            assert t.is_cuda and t.is_contiguous()
+        t = trd_tracklets(y.data_ptr(), z.data_ptr(), dy.data_ptr(), det_row.data_ptr(),
+                          group.data_ptr() if group is not None else None)
+        trd_load_tracklets(self.ctx, t, y.numel(), n_groups, _stream_handle(stream))
+        self.n_tracklets = int(y.numel())
+        self.n_groups = int(n_groups)
+
+    def alloc_results(self, n, chi2_layer=True):
+        import torch
+        dev = torch.device("cuda", self.device)
+        f = self.fdtype
+        return dict(
+            idx=torch.empty((6, n), dtype=torch.int32, device=dev),
+            p=torch.empty((5, n), dtype=f, device=dev),
+            cov=torch.empty((15, n), dtype=f, device=dev),
+            x=torch.empty(n, dtype=f, device=dev),
+            sector=torch.empty(n, dtype=torch.int32, device=dev),
+            chi2=torch.empty(n, dtype=f, device=dev),
+            chi2_layer=torch.empty((6, n), dtype=f, device=dev) if chi2_layer else None,
+            n_match=torch.empty(n, dtype=torch.int32, device=dev),
+            status=torch.empty(n, dtype=torch.int32, device=dev),
+        )
+
+    def match(self, p, cov, x, sector, group=None, out=None, stream=None):
+        n = int(x.numel())
+        for t in (p, cov, x):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == self.fdtype
+        assert sector.is_cuda and sector.is_contiguous()
+        if out is None:
+            out = self.alloc_results(n)
+        trk = trd_tracks(p.data_ptr(), cov.data_ptr(), x.data_ptr(), sector.data_ptr(),
+                         group.data_ptr() if group is not None else None)
+        res = trd_results(*(None if out[k] is None else out[k].data_ptr() for k in
+                            ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status")))
+        trd_match(self.ctx, trk, n, res, _stream_handle(stream))
+        return out
+
+    def binning(self, stream=None):
+        """(offsets[n_cells+1] uint32 as int32, sorted[n_valid, 4] float32) copies."""
+        import torch
+        v = trd_get_binning(self.ctx)
+        dev = torch.device("cuda", self.device)
+        off = torch.empty(v.n_cells + 1, dtype=torch.int32, device=dev)
+        srt = torch.empty((max(v.n_tracklets, 1), 4), dtype=torch.float32, device=dev)
+        trd_copy_binning(self.ctx, off.data_ptr(), srt.data_ptr(), max(v.n_tracklets, 1),
+                         _stream_handle(stream))
+        return off, srt
+
+    @property
+    def device_bytes(self):
+        return trd_device_bytes(self.ctx)
+
+
+def device_inputs(dev_layout, precision="fp32", device=0):
+    """Device tensors from synth.to_device_layout() arrays."""
+    import numpy as np
+    import torch
+    d = torch.device("cuda", device)
+    f = np.float64 if precision == "fp64" else np.float32
+
+    def T(a, dt=None):
+        a = np.ascontiguousarray(a if dt is None else a.astype(dt))
+        return torch.from_numpy(a).to(d)
+
+    L = dev_layout
+    return dict(
+        p=T(L["p32"], f), cov=T(L["cov32"], f), x=T(L["x32"], f), sector=T(L["sector"]),
+        group=T(L["group"]), y=T(L["y32"]), z=T(L["z32"]), dy=T(L["dy32"]),
+        det_row=T(L["det_row"].view(np.int32)), tgroup=T(L["tgroup"]),
+    )

@@ -1,0 +1,440 @@
+// Host side of the C ABI (include/trd.h): configuration checks, the
+// context's device buffers, and the stream-ordered launch sequences of
+// trd_load_tracklets and trd_match.  Nothing here synchronises the stream
+// except trd_reserve/trd_destroy (allocation, free).
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "../../include/trd.h"
+#include "trd_internal.h"
+
+using namespace trd;
+
+struct trd_ctx {
+    int device = 0;
+    trd_config cfg{};
+    DevCfg<double> gd{};
+    DevCfg<float> gf{};
+    double *d_dx64 = nullptr;
+    float *d_dx32 = nullptr;
+    uint32_t *d_small = nullptr;  // [0] fb_count [1] fb_done [2] n_big
+
+    // tracklet-side capacity
+    int64_t cap_tkl = 0;
+    uint32_t *d_key = nullptr, *d_rank = nullptr, *d_big = nullptr;
+    float4 *d_sorted = nullptr, *d_tmp = nullptr;
+    // cell-side capacity (entries of count/offsets)
+    int64_t cap_cells = 0;
+    uint32_t *d_count = nullptr, *d_offsets = nullptr, *d_bsums = nullptr;
+    // track-side capacity
+    int64_t cap_trk = 0;
+    int32_t *d_fb = nullptr;
+
+    int64_t bytes = 0;
+    bool loaded = false;
+    int64_t n_tkl = 0;
+    int32_t n_groups = 0;
+    int64_t n_cells = 0;
+};
+
+namespace {
+
+bool finite_all(const double *v, int n)
+{
+    for (int i = 0; i < n; i++)
+        if (!isfinite(v[i])) return false;
+    return true;
+}
+
+int check_config(const trd_config *c)
+{
+    if (!c || c->struct_size != sizeof(trd_config)) return TRD_EINVAL;
+    if (c->precision < TRD_PREC_FP64 || c->precision > TRD_PREC_FP32_COV64) return TRD_EINVAL;
+    if (c->n_rows < 1 || c->n_rows > 32 || c->n_yb < 1 || c->n_yb > 4096) return TRD_EINVAL;
+    if (!(c->y_bin_w > 0) || !isfinite(c->y_bin_w)) return TRD_EINVAL;
+    int ex;
+    if (frexp(c->y_bin_w, &ex) != 0.5) return TRD_EINVAL;  // power of two
+    if (!finite_all(c->x_layer, 6) || !finite_all(c->tilt, 6) || !finite_all(c->dx_chamber, 540))
+        return TRD_EINVAL;
+    for (int l = 0; l < 6; l++)
+        if (!(c->x_layer[l] > 0)) return TRD_EINVAL;
+    const double sc[] = {c->z_min, c->pad_len, c->drift_len, c->bz, c->x_over_x0, c->mass,
+                         c->tan_psi, c->chi2_max, c->n_sigma_dy, c->n_sigma_road, c->snp_max};
+    if (!finite_all(sc, 11) || !finite_all(c->sigma_y, 3) || !finite_all(c->sigma_dy, 3))
+        return TRD_EINVAL;
+    if (!(c->pad_len > 0) || !(c->z_min < 0) || !(c->snp_max > 0 && c->snp_max <= 1) ||
+        !(c->n_sigma_road > 0) || !(c->n_sigma_dy > 0) || !(c->chi2_max > 0) || c->x_over_x0 < 0)
+        return TRD_EINVAL;
+    // the stacks' pad rows tile [z_min, -z_min]
+    if (fabs(2 * c->z_min + TRD_N_STACKS * c->n_rows * c->pad_len) > 1e-9 * fabs(c->z_min))
+        return TRD_EINVAL;
+    if (c->block_size != 0 && (c->block_size < 64 || c->block_size > 256 || c->block_size % 64))
+        return TRD_EINVAL;
+    switch (c->search_lanes) {
+    case 0: case 1: case 4: case 8: case 16: case 32: case 64: break;
+    default: return TRD_EINVAL;
+    }
+    if (c->reserved != 0) return TRD_EINVAL;
+    return TRD_OK;
+}
+
+template <typename T>
+void fill_devcfg(DevCfg<T> &g, const trd_config &c, const T *dx)
+{
+    for (int l = 0; l < 6; l++) {
+        g.x_layer[l] = (T)c.x_layer[l];
+        g.tilt[l] = (T)c.tilt[l];
+    }
+    g.z_min = (T)c.z_min;
+    g.z_max = (T)(-c.z_min);
+    g.pad_len = (T)c.pad_len;
+    g.inv_pad = (T)(1.0 / c.pad_len);
+    g.vz = (T)(c.pad_len * c.pad_len / 12.0);
+    g.drift_len = (T)c.drift_len;
+    g.k_curv = (T)(-2.99792458e-3 * c.bz);
+    g.x_over_x0 = (T)c.x_over_x0;
+    g.mass2 = (T)(c.mass * c.mass);
+    for (int k = 0; k < 3; k++) {
+        g.sigma_y[k] = (T)c.sigma_y[k];
+        g.sigma_dy[k] = (T)c.sigma_dy[k];
+    }
+    g.tan_psi = (T)c.tan_psi;
+    g.chi2_max = (T)c.chi2_max;
+    g.n_sigma_dy = (T)c.n_sigma_dy;
+    g.n_sigma_road = (T)c.n_sigma_road;
+    g.snp_max = (T)c.snp_max;
+    const double dphi = 2.0 * M_PI / TRD_N_SECTORS;
+    g.tan_half_sector = (T)tan(0.5 * dphi);
+    g.cos_sector = (T)cos(dphi);
+    g.sin_sector = (T)sin(dphi);
+    double dxm = 0;
+    for (int d = 0; d < TRD_N_DET; d++) dxm = fmax(dxm, fabs(c.dx_chamber[d]));
+    g.dx_max = (T)dxm;
+    g.dx = dx;
+    g.bin.y_min = -c.y_bin_w * c.n_yb / 2.0;
+    g.bin.inv_w = 1.0 / c.y_bin_w;
+    g.bin.n_rows = c.n_rows;
+    g.bin.n_yb = c.n_yb;
+    g.bin.n_groups = 1;
+    g.bin.n_cells = 0;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? TRD_OK : TRD_EDEVICE; }
+
+template <typename T>
+int dev_alloc(trd_ctx *ctx, T **p, int64_t count, int64_t *bytes_acc)
+{
+    const size_t sz = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    void *q = nullptr;
+    if (hipMalloc(&q, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return TRD_ENOMEM;
+    }
+    *p = static_cast<T *>(q);
+    *bytes_acc += (int64_t)sz;
+    (void)ctx;
+    return TRD_OK;
+}
+
+template <typename T> void dev_free(T **p)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+int64_t tkl_bytes(int64_t n) { return (int64_t)(n > 0 ? n : 1) * (4 + 4 + 16 + 16) + 4 * (n / 32 + 2); }
+int64_t cell_bytes(int64_t nc) { return 8 * (nc + 1) + 4 * scan_block_sums_len(nc + 1); }
+int64_t trk_bytes(int64_t n) { return 4 * (n > 0 ? n : 1); }
+
+int over_budget(const trd_ctx *ctx, int64_t extra)
+{
+    const uint64_t b = ctx->cfg.hbm_budget_bytes;
+    return b != 0 && (uint64_t)(ctx->bytes + extra) > b;
+}
+
+int ensure_tkl(trd_ctx *ctx, int64_t n)
+{
+    if (n <= ctx->cap_tkl && ctx->d_key) return TRD_OK;
+    int64_t cap = n > 2 * ctx->cap_tkl ? n : 2 * ctx->cap_tkl;
+    const int64_t old = ctx->d_key ? tkl_bytes(ctx->cap_tkl) : 0;
+    if (over_budget(ctx, tkl_bytes(cap) - old)) {
+        cap = n;
+        if (over_budget(ctx, tkl_bytes(cap) - old)) return TRD_EBUDGET;
+    }
+    dev_free(&ctx->d_key);
+    dev_free(&ctx->d_rank);
+    dev_free(&ctx->d_sorted);
+    dev_free(&ctx->d_tmp);
+    dev_free(&ctx->d_big);
+    ctx->bytes -= old;
+    ctx->cap_tkl = 0;
+    int64_t acc = 0;
+    int rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_key, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_rank, cap, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_sorted, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_tmp, cap, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_big, cap / 32 + 2, &acc))) {
+        dev_free(&ctx->d_key);
+        dev_free(&ctx->d_rank);
+        dev_free(&ctx->d_sorted);
+        dev_free(&ctx->d_tmp);
+        dev_free(&ctx->d_big);
+        return rc;
+    }
+    ctx->bytes += tkl_bytes(cap);
+    ctx->cap_tkl = cap;
+    return TRD_OK;
+}
+
+int ensure_cells(trd_ctx *ctx, int64_t nc)
+{
+    if (nc <= ctx->cap_cells && ctx->d_count) return TRD_OK;
+    const int64_t old = ctx->d_count ? cell_bytes(ctx->cap_cells) : 0;
+    if (over_budget(ctx, cell_bytes(nc) - old)) return TRD_EBUDGET;
+    dev_free(&ctx->d_count);
+    dev_free(&ctx->d_offsets);
+    dev_free(&ctx->d_bsums);
+    ctx->bytes -= old;
+    ctx->cap_cells = 0;
+    int64_t acc = 0;
+    int rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_count, nc + 1, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_offsets, nc + 1, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_bsums, scan_block_sums_len(nc + 1), &acc))) {
+        dev_free(&ctx->d_count);
+        dev_free(&ctx->d_offsets);
+        dev_free(&ctx->d_bsums);
+        return rc;
+    }
+    ctx->bytes += cell_bytes(nc);
+    ctx->cap_cells = nc;
+    return TRD_OK;
+}
+
+int ensure_trk(trd_ctx *ctx, int64_t n)
+{
+    if (n <= ctx->cap_trk && ctx->d_fb) return TRD_OK;
+    int64_t cap = n > 2 * ctx->cap_trk ? n : 2 * ctx->cap_trk;
+    const int64_t old = ctx->d_fb ? trk_bytes(ctx->cap_trk) : 0;
+    if (over_budget(ctx, trk_bytes(cap) - old)) {
+        cap = n;
+        if (over_budget(ctx, trk_bytes(cap) - old)) return TRD_EBUDGET;
+    }
+    dev_free(&ctx->d_fb);
+    ctx->bytes -= old;
+    ctx->cap_trk = 0;
+    int64_t acc = 0;
+    int rc = dev_alloc(ctx, &ctx->d_fb, cap, &acc);
+    if (rc) return rc;
+    ctx->bytes += trk_bytes(cap);
+    ctx->cap_trk = cap;
+    return TRD_OK;
+}
+
+int64_t n_cells_of(const trd_config &c, int32_t ng)
+{
+    return (int64_t)ng * TRD_N_DET * c.n_rows * c.n_yb;
+}
+
+int launch_status()
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TRD_OK : TRD_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int trd_create(const trd_config *cfg, int device, trd_ctx **out)
+{
+    if (!out) return TRD_EINVAL;
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (cfg->flags & TRD_CFG_FAIL_ALLOC) return TRD_ENOMEM;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return device < 0 ? TRD_EINVAL : TRD_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return TRD_EDEVICE;
+    trd_ctx *ctx = new (std::nothrow) trd_ctx();
+    if (!ctx) return TRD_ENOMEM;
+    ctx->device = device;
+    ctx->cfg = *cfg;
+    int64_t acc = 0;
+    if ((rc = dev_alloc(ctx, &ctx->d_dx64, TRD_N_DET, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_dx32, TRD_N_DET, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_small, 4, &acc))) {
+        trd_destroy(ctx);
+        return rc;
+    }
+    ctx->bytes += acc;
+    float dx32[TRD_N_DET];
+    for (int d = 0; d < TRD_N_DET; d++) dx32[d] = (float)cfg->dx_chamber[d];
+    if (hipMemcpy(ctx->d_dx64, cfg->dx_chamber, sizeof(double) * TRD_N_DET, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(ctx->d_dx32, dx32, sizeof(float) * TRD_N_DET, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(ctx->d_small, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        trd_destroy(ctx);
+        return TRD_EDEVICE;
+    }
+    fill_devcfg(ctx->gd, *cfg, (const double *)ctx->d_dx64);
+    fill_devcfg(ctx->gf, *cfg, (const float *)ctx->d_dx32);
+    if (ctx->cfg.block_size == 0) ctx->cfg.block_size = 256;
+    if (ctx->cfg.search_lanes == 0) ctx->cfg.search_lanes = 8;
+    *out = ctx;
+    return TRD_OK;
+}
+
+int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t max_tracks)
+{
+    if (!ctx || max_tracklets < 0 || max_groups < 1 || max_tracks < 0) return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    const int64_t nc = n_cells_of(ctx->cfg, max_groups);
+    if (nc >= (int64_t)UINT32_MAX - 1 || max_tracklets >= (int64_t)INT32_MAX) return TRD_EINVAL;
+    int rc;
+    if ((rc = ensure_tkl(ctx, max_tracklets)) || (rc = ensure_cells(ctx, nc)) ||
+        (rc = ensure_trk(ctx, max_tracks)))
+        return rc;
+    return hip_status(hipDeviceSynchronize());
+}
+
+int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t n_groups,
+                       void *hip_stream)
+{
+    if (!ctx || !t || n < 0 || n_groups < 1) return TRD_EINVAL;
+    if (n > 0 && (!t->y || !t->z || !t->dy || !t->det_row)) return TRD_EINVAL;
+    if (n >= (int64_t)INT32_MAX) return TRD_EINVAL;
+    const int64_t nc = n_cells_of(ctx->cfg, n_groups);
+    if (nc >= (int64_t)UINT32_MAX - 1) return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    int rc;
+    if ((rc = ensure_tkl(ctx, n)) || (rc = ensure_cells(ctx, nc))) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    BinCfg b = ctx->gd.bin;
+    b.n_groups = n_groups;
+    b.n_cells = (uint32_t)nc;
+    ctx->gd.bin = b;
+    ctx->gf.bin = b;
+    launch_fill_u32(ctx->d_count, 0u, nc + 1, s);
+    launch_key_hist(t->y, t->z, t->dy, t->det_row, t->group, n, b, ctx->d_key, ctx->d_rank,
+                    ctx->d_count, s);
+    launch_scan(ctx->d_count, nc, ctx->d_bsums, ctx->d_offsets, s);
+    launch_scatter(t->y, t->z, t->dy, ctx->d_key, ctx->d_rank, ctx->d_offsets, n, (uint32_t)nc,
+                   ctx->d_sorted, s);
+    launch_cell_sort(ctx->d_offsets, (uint32_t)nc, ctx->d_sorted, ctx->d_tmp, ctx->d_big,
+                     ctx->d_small + 2, s);
+    if ((rc = launch_status())) return rc;
+    ctx->loaded = true;
+    ctx->n_tkl = n;
+    ctx->n_groups = n_groups;
+    ctx->n_cells = nc;
+    return TRD_OK;
+}
+
+int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream)
+{
+    if (!ctx || !in || !out || n < 0) return TRD_EINVAL;
+    if (!ctx->loaded) return TRD_ESTATE;
+    if (n == 0) return TRD_OK;
+    if (n >= (int64_t)INT32_MAX) return TRD_EINVAL;
+    if (!in->p || !in->cov || !in->x || !in->sector || !out->idx || !out->p || !out->cov ||
+        !out->x || !out->sector || !out->chi2 || !out->n_match || !out->status)
+        return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    int rc;
+    if (ctx->cfg.precision == TRD_PREC_FP32 && (rc = ensure_trk(ctx, n))) return rc;
+    MatchIO io{};
+    io.sorted = ctx->d_sorted;
+    io.offsets = ctx->d_offsets;
+    io.ip = in->p;
+    io.ic = in->cov;
+    io.ix = in->x;
+    io.isec = in->sector;
+    io.igrp = in->group;
+    io.n = n;
+    io.oidx = out->idx;
+    io.op = out->p;
+    io.oc = out->cov;
+    io.ox = out->x;
+    io.osec = out->sector;
+    io.ochi2 = out->chi2;
+    io.ochi2l = out->chi2_layer;
+    io.onm = out->n_match;
+    io.ost = out->status;
+    io.fb_list = ctx->d_fb;
+    io.fb_count = ctx->d_small;
+    io.fb_done = ctx->d_small + 1;
+    io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
+    launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size,
+                 ctx->cfg.search_lanes, (hipStream_t)hip_stream);
+    return launch_status();
+}
+
+int trd_get_binning(trd_ctx *ctx, trd_binning_view *out)
+{
+    if (!ctx || !out) return TRD_EINVAL;
+    if (!ctx->loaded) return TRD_ESTATE;
+    out->offsets = ctx->d_offsets;
+    out->sorted = reinterpret_cast<const float *>(ctx->d_sorted);
+    out->n_cells = ctx->n_cells;
+    out->n_tracklets = ctx->n_tkl;
+    return TRD_OK;
+}
+
+int trd_copy_binning(trd_ctx *ctx, uint32_t *offsets_out, float *sorted_out, int64_t max_valid,
+                     void *hip_stream)
+{
+    if (!ctx || !offsets_out || (!sorted_out && max_valid > 0) || max_valid < 0) return TRD_EINVAL;
+    if (!ctx->loaded) return TRD_ESTATE;
+    if (max_valid < ctx->n_tkl) return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (hipMemcpyAsync(offsets_out, ctx->d_offsets, sizeof(uint32_t) * (size_t)(ctx->n_cells + 1),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return TRD_EDEVICE;
+    if (ctx->n_tkl > 0 &&
+        hipMemcpyAsync(sorted_out, ctx->d_sorted, sizeof(float4) * (size_t)ctx->n_tkl,
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return TRD_EDEVICE;
+    return TRD_OK;
+}
+
+int64_t trd_device_bytes(const trd_ctx *ctx) { return ctx ? ctx->bytes : 0; }
+
+void trd_destroy(trd_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    dev_free(&ctx->d_dx64);
+    dev_free(&ctx->d_dx32);
+    dev_free(&ctx->d_small);
+    dev_free(&ctx->d_key);
+    dev_free(&ctx->d_rank);
+    dev_free(&ctx->d_sorted);
+    dev_free(&ctx->d_tmp);
+    dev_free(&ctx->d_big);
+    dev_free(&ctx->d_count);
+    dev_free(&ctx->d_offsets);
+    dev_free(&ctx->d_bsums);
+    dev_free(&ctx->d_fb);
+    delete ctx;
+}
+
+const char *trd_status_string(int code)
+{
+    switch (code) {
+    case TRD_OK: return "ok";
+    case TRD_EINVAL: return "invalid argument";
+    case TRD_ENOMEM: return "device allocation failed";
+    case TRD_EDEVICE: return "HIP device error";
+    case TRD_ESTATE: return "no tracklets loaded";
+    case TRD_EBUDGET: return "HBM budget exceeded";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP translation units of libtrd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trd {
+
+constexpr int kLayers = 6;
+constexpr int kSectors = 18;
+constexpr int kStacks = 5;
+constexpr int kDet = 540;
+
+// per-track status bits (same values as TRD_TRK_* of the public header)
+constexpr uint32_t kStopSnp = 1u, kRotFail = 2u, kOutOfZ = 4u, kFallback = 8u, kNotPD = 16u,
+                   kBadInput = 32u;
+
+// Cell geometry of the tracklet binning; the key arithmetic runs in double
+// so that floor() sees the exact difference y - y_min (w is a power of two).
+struct BinCfg {
+    double y_min;   // -w * n_yb / 2
+    double inv_w;   // 1 / w, exact
+    int32_t n_rows, n_yb, n_groups;
+    uint32_t n_cells;
+};
+
+// Matching parameters, converted once to the state precision T.
+template <typename T>
+struct DevCfg {
+    T x_layer[kLayers];
+    T tilt[kLayers];
+    T z_min, z_max, pad_len, inv_pad, vz;  // vz = pad_len^2 / 12
+    T drift_len, k_curv;                   // k_curv = -kappa * Bz
+    T x_over_x0, mass2;
+    T sigma_y[3], sigma_dy[3], tan_psi;
+    T chi2_max, n_sigma_dy, n_sigma_road, snp_max;
+    T tan_half_sector, cos_sector, sin_sector;  // tan(10 deg), cos/sin(20 deg)
+    T dx_max;
+    const T *dx;                               // [540] device
+    BinCfg bin;
+};
+
+// launchers (stream-ordered, no synchronisation)
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void launch_key_hist(const float *y, const float *z, const float *dy, const uint32_t *det_row,
+                     const int32_t *grp, int64_t n, const BinCfg &b, uint32_t *key,
+                     uint32_t *rank, uint32_t *count, hipStream_t s);
+void launch_scan(const uint32_t *count, int64_t n, uint32_t *block_sums, uint32_t *offsets,
+                 hipStream_t s);
+int64_t scan_block_sums_len(int64_t n);
+void launch_scatter(const float *y, const float *z, const float *dy, const uint32_t *key,
+                    const uint32_t *rank, const uint32_t *offsets, int64_t n, uint32_t n_cells,
+                    float4 *sorted, hipStream_t s);
+void launch_cell_sort(const uint32_t *offsets, uint32_t n_cells, float4 *sorted, float4 *tmp,
+                      uint32_t *big_list, uint32_t *n_big, hipStream_t s);
+
+struct MatchIO {
+    const float4 *sorted;
+    const uint32_t *offsets;
+    const void *ip, *ic, *ix;
+    const int32_t *isec, *igrp;
+    int64_t n;
+    int32_t *oidx;
+    void *op, *oc, *ox;
+    int32_t *osec;
+    void *ochi2, *ochi2l;
+    int32_t *onm;
+    uint32_t *ost;
+    int32_t *fb_list;    // FP32 mode: tracks to re-run with a double covariance
+    uint32_t *fb_count;  // [1]
+    uint32_t *fb_done;   // [1]
+    int force_fallback;  // test hook: queue every track for the re-run
+};
+
+// precision: 0 = FP64, 1 = FP32 (+ fallback), 2 = FP32 state / FP64 covariance
+// lanes: lanes that scan one track's road together (1 = one lane per track)
+void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
+                  const MatchIO &io, int block, int lanes, hipStream_t s);
+
+}  // namespace trd

@@ -1,0 +1,787 @@
+// Track-to-tracklet matching for gfx950: one seed track per lane.
+//
+// Per layer (Sect. 3 of the paper): propagate the helix state and its
+// covariance to the chamber plane, hop into the neighbouring sector frame if
+// the point left the sector, add the layer's multiple scattering, open the
+// covariance road, scan the tracklet cells the road overlaps (linear
+// extrapolation to each chamber's radius, pad-tilt corrected y residual, dy
+// exclusion at n sigma, chi2 from y and z only), keep the lexicographic best
+// (chi2, tracklet index), propagate precisely to the winner's radius and run
+// the Joseph-form Kalman update.
+//
+// TS is the precision of the state and of the candidate gates, TC that of
+// the covariance.  <double,double> is the plain double-precision matcher,
+// <float,float> the fast one whose tracks are re-run as <float,double> when
+// the float covariance stops being positive definite.
+#include "trd_internal.h"
+
+namespace trd {
+
+namespace {
+
+// packed upper triangle of the symmetric 5x5 covariance, row-major
+enum : int {
+    YY = 0, YZ, YS, YT, YC,
+    ZZ, ZS, ZT, ZC,
+    SS, ST, SC,
+    TT, TC_,
+    CC
+};
+
+template <typename TS, typename TC>
+struct Trk {
+    TS y, z, s, t, c, x;
+    TC C[15];
+    int sec;
+};
+
+template <typename T> __device__ __forceinline__ T sq(T a) { return a * a; }
+
+template <typename T> __device__ __forceinline__ T sinc_(T u) { return u == T(0) ? T(1) : sin(u) / u; }
+
+// (sin d - d) / d^2; Taylor series below |d| = 0.5 where the direct form cancels
+template <typename T> __device__ __forceinline__ T gfun(T d)
+{
+    if (fabs(d) < T(0.5)) {
+        const T d2 = d * d;
+        T term = -d / T(6), sum = T(0);
+#pragma unroll
+        for (int k = 1; k <= 8; k++) {
+            sum += term;
+            term *= -d2 / (T(2 * k + 2) * T(2 * k + 3));
+        }
+        return sum;
+    }
+    return (sin(d) - d) / (d * d);
+}
+
+// Helix step in the sector frame from T.x to x2, with the exact Jacobian
+// applied to the covariance.  False (state untouched) if |sin phi| would
+// reach snp_max.
+template <typename TS, typename TC>
+__device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS> &g)
+{
+    const TS dx = x2 - T.x;
+    const TS k = g.k_curv;
+    const TS cu = k * T.c;
+    const TS s1 = T.s;
+    const TS s2 = s1 + cu * dx;
+    if (!(fabs(s2) < g.snp_max)) return false;
+    const TS f1 = sqrt(TS(1) - s1 * s1);
+    const TS f2 = sqrt(TS(1) - s2 * s2);
+    const TS ff = f1 + f2;
+    const TS dy = dx * (s1 + s2) / ff;
+    const TS chord = sqrt(dx * dx + dy * dy);
+    const TS h = TS(0.5) * fabs(cu) * chord;
+    const TS aoh = h > TS(0) ? asin(h) / h : TS(1);
+    const TS arc = (dx >= TS(0) ? chord : -chord) * aoh;
+    const TS delta = cu * arc;
+    const TS t = T.t;
+
+    // Jacobian entries (identity elsewhere)
+    const TC f12 = TC(f1) * TC(f2);
+    const TC a = TC(arc) * sinc_(TC(delta)) / f12;                        // dy/ds
+    const TC b = TC(k) * sq(TC(dx)) / TC(ff) *
+                 (TC(1) + TC(s2) * TC(s1 + s2) / (TC(f2) * TC(ff)));        // dy/dc
+    const TC d = TC(t) * TC(dy) / f12;                                      // dz/ds
+    const TC e = TC(arc);                                                   // dz/dt
+    const TC sh = sinc_(TC(0.5) * TC(delta));
+    const TC f = TC(k) * TC(t) * sq(TC(arc)) *
+                 ((TC(s2) / TC(f2)) * sh * sh * TC(0.5) + gfun(TC(delta)));  // dz/dc
+    const TC gg = TC(k) * TC(dx);                                           // ds/dc
+
+    T.y += dy;
+    T.z += t * arc;
+    T.s = s2;
+    T.x = x2;
+
+    TC *C = T.C;
+    // D = J C (rows y, z, s change)
+    const TC D00 = C[YY] + a * C[YS] + b * C[YC];
+    const TC D01 = C[YZ] + a * C[ZS] + b * C[ZC];
+    const TC D02 = C[YS] + a * C[SS] + b * C[SC];
+    const TC D03 = C[YT] + a * C[ST] + b * C[TC_];
+    const TC D04 = C[YC] + a * C[SC] + b * C[CC];
+    const TC D11 = C[ZZ] + d * C[ZS] + e * C[ZT] + f * C[ZC];
+    const TC D12 = C[ZS] + d * C[SS] + e * C[ST] + f * C[SC];
+    const TC D13 = C[ZT] + d * C[ST] + e * C[TT] + f * C[TC_];
+    const TC D14 = C[ZC] + d * C[SC] + e * C[TC_] + f * C[CC];
+    const TC D22 = C[SS] + gg * C[SC];
+    const TC D23 = C[ST] + gg * C[TC_];
+    const TC D24 = C[SC] + gg * C[CC];
+    // C' = D J^T
+    C[YY] = D00 + a * D02 + b * D04;
+    C[YZ] = D01 + d * D02 + e * D03 + f * D04;
+    C[YS] = D02 + gg * D04;
+    C[YT] = D03;
+    C[YC] = D04;
+    C[ZZ] = D11 + d * D12 + e * D13 + f * D14;
+    C[ZS] = D12 + gg * D14;
+    C[ZT] = D13;
+    C[ZC] = D14;
+    C[SS] = D22 + gg * D24;
+    C[ST] = D23;
+    C[SC] = D24;
+    return true;
+}
+
+// Change of sector frame by +-20 degrees at the current point.
+template <typename TS, typename TC>
+__device__ __forceinline__ bool rotate(Trk<TS, TC> &T, bool up, const DevCfg<TS> &g)
+{
+    const TS ca = g.cos_sector, sa = up ? g.sin_sector : -g.sin_sector;
+    const TS s = T.s, f = sqrt(TS(1) - s * s);
+    const TS s1 = s * ca - f * sa;
+    const TS f1 = f * ca + s * sa;
+    if (!(f1 > TS(0))) return false;
+    const TS x1 = T.x * ca + T.y * sa;
+    const TS y1 = -T.x * sa + T.y * ca;
+    const TC A = TC(f) / TC(f1);
+    const TC B = -TC(sa) * TC(T.t) / TC(f1);
+    const TC Cc = -TC(g.k_curv) * TC(T.c) * TC(sa);
+    const TC Dd = TC(f1) / TC(f);
+    T.y = y1;
+    T.s = s1;
+    T.x = x1;
+    TC *C = T.C;
+    const TC c00 = C[YY], c01 = C[YZ], c02 = C[YS], c03 = C[YT], c04 = C[YC];
+    const TC D10 = c01 + B * c00, D12 = C[ZS] + B * c02;
+    const TC D20 = Cc * c00 + Dd * c02, D22 = Cc * c02 + Dd * C[SS];
+    C[YY] = A * A * c00;
+    C[YZ] = A * c01 + B * A * c00;
+    C[YS] = Cc * A * c00 + Dd * A * c02;
+    C[YT] = A * c03;
+    C[YC] = A * c04;
+    C[ZZ] = (C[ZZ] + B * c01) + B * D10;
+    C[ZS] = Cc * D10 + Dd * D12;
+    C[ZT] = C[ZT] + B * c03;
+    C[ZC] = C[ZC] + B * c04;
+    C[SS] = Cc * D20 + Dd * D22;
+    C[ST] = Cc * c03 + Dd * C[ST];
+    C[SC] = Cc * c04 + Dd * C[SC];
+    return true;
+}
+
+// Thin scatterer (Highland width) at the current point.
+template <typename TS, typename TC>
+__device__ __forceinline__ void add_ms(Trk<TS, TC> &T, const DevCfg<TS> &g)
+{
+    const TC c = TC(T.c), t = TC(T.t), s = TC(T.s);
+    if (c == TC(0) || !(g.x_over_x0 > TS(0))) return;
+    const TC f = sqrt(TC(1) - s * s);
+    const TC tt = TC(1) + t * t;
+    const TC pp = sqrt(tt) / fabs(c);
+    const TC beta = pp / sqrt(pp * pp + TC(g.mass2));
+    const TC xi = TC(g.x_over_x0) * sqrt(tt) / f;
+    const TC th0 = TC(0.0136) / (beta * pp) * sqrt(xi) * (TC(1) + TC(0.038) * log(xi));
+    const TC th2 = th0 * th0;
+    T.C[SS] += th2 * f * f * tt;
+    T.C[TT] += th2 * tt * tt;
+    T.C[CC] += th2 * c * c * t * t;
+    T.C[TC_] += th2 * tt * c * t;
+}
+
+template <typename T> __device__ __forceinline__ T cget(const T *C, int i, int j)
+{
+    // symmetric access into the packed upper triangle
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    const int off = a * 5 - (a * (a - 1)) / 2 + (b - a);
+    return C[off];
+}
+
+// positive definiteness of the packed covariance: all LDL^T pivots > 0
+template <typename TC> __device__ __forceinline__ bool ldl_pd(const TC *C)
+{
+    TC L[5][5], dd[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        TC v = cget(C, j, j);
+#pragma unroll
+        for (int k2 = 0; k2 < j; k2++) v -= L[j][k2] * L[j][k2] * dd[k2];
+        if (!(v > TC(0))) return false;
+        dd[j] = v;
+#pragma unroll
+        for (int i = j + 1; i < 5; i++) {
+            TC w = cget(C, i, j);
+#pragma unroll
+            for (int k2 = 0; k2 < j; k2++) w -= L[i][k2] * L[j][k2] * dd[k2];
+            L[i][j] = w / v;
+        }
+    }
+    return true;
+}
+
+// Joseph-form update with h(p) = (y + tau (z - z_tkl), z); returns false if
+// the updated covariance is not positive definite (LDL^T pivots).
+template <typename TS, typename TC>
+__device__ __forceinline__ bool kalman_update(Trk<TS, TC> &T, TS ry, TS rz, TS tau, TC vy, TC vz)
+{
+    TC *C = T.C;
+    const TC tc = TC(tau);
+    TC H0[5], H1[5];  // C H^T columns
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        H0[i] = cget(C, i, 0) + tc * cget(C, i, 1);
+        H1[i] = cget(C, i, 1);
+    }
+    const TC S00 = H0[0] + tc * H0[1] + vy;
+    const TC S01 = H1[0] + tc * H1[1];
+    const TC S11 = H1[1] + vz;
+    const TC det = S00 * S11 - S01 * S01;
+    const TC i00 = S11 / det, i01 = -S01 / det, i11 = S00 / det;
+    TC K0[5], K1[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        K0[i] = H0[i] * i00 + H1[i] * i01;
+        K1[i] = H0[i] * i01 + H1[i] * i11;
+    }
+    T.y += TS(K0[0] * TC(ry) + K1[0] * TC(rz));
+    T.z += TS(K0[1] * TC(ry) + K1[1] * TC(rz));
+    T.s += TS(K0[2] * TC(ry) + K1[2] * TC(rz));
+    T.t += TS(K0[3] * TC(ry) + K1[3] * TC(rz));
+    T.c += TS(K0[4] * TC(ry) + K1[4] * TC(rz));
+    // B = (I - K H) C
+    TC B[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+        for (int j = 0; j < 5; j++) B[i][j] = cget(C, i, j) - K0[i] * H0[j] - K1[i] * H1[j];
+    // C' = B (I - K H)^T + K V K^T
+    TC Bh0[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) Bh0[i] = B[i][0] + tc * B[i][1];
+    int o = 0;
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+        for (int j = i; j < 5; j++) {
+            C[o++] = B[i][j] - Bh0[i] * K0[j] - B[i][1] * K1[j] + vy * K0[i] * K0[j] +
+                     vz * K1[i] * K1[j];
+        }
+    return ldl_pd(C);
+}
+
+template <typename TS> __device__ __forceinline__ TS poly2(const TS *a, TS s)
+{
+    return a[0] + a[1] * s + a[2] * s * s;
+}
+
+// y bin of a window edge, clamped; NaN maps to bin 0 (never out of range)
+__device__ __forceinline__ int ybin(double y, const BinCfg &b)
+{
+    const double u = floor((y - b.y_min) * b.inv_w);
+    if (!(u >= 0.0)) return 0;
+    return u > (double)(b.n_yb - 1) ? b.n_yb - 1 : (int)u;
+}
+
+// global pad-row index of a z window edge, clamped to [0, nrt - 1]
+template <typename TS> __device__ __forceinline__ int zrow(TS z, const DevCfg<TS> &g, int nrt)
+{
+    const TS u = floor((z - g.z_min) * g.inv_pad);
+    if (!(u >= TS(0))) return 0;
+    return u > TS(nrt - 1) ? nrt - 1 : (int)u;
+}
+
+
+// ---------------------------------------------------------------------------
+// per-track phases shared by the kernels
+// ---------------------------------------------------------------------------
+
+// Search road of one track at one layer.
+template <typename TS>
+struct Road {
+    TS y, z, tphi, tz, tau, Ry, Rz, gdy, dytrk, si00, si01, si11;
+    int glo, ghi;  // global pad-row range (glo > ghi: nothing to search)
+    int yb0, yb1;  // y-bin range
+    int gdet0;     // key-space chamber of stack 0: group * 540 + sector * 30 + layer
+    int sdet0;     // misalignment-table chamber of stack 0: sector * 30 + layer
+};
+
+// Best candidate so far: lexicographic minimum of (chi2, input index).
+template <typename TS>
+struct Best {
+    TS chi2;
+    int idx;    // input-order tracklet index, INT_MAX if none
+    int pos;    // sorted position of the record
+    int stack;  // stack of its chamber
+};
+
+template <typename TS> __device__ __forceinline__ Best<TS> no_best()
+{
+    Best<TS> b;
+    b.chi2 = TS(INFINITY);
+    b.idx = 0x7fffffff;
+    b.pos = 0;
+    b.stack = 0;
+    return b;
+}
+
+template <typename TS> __device__ __forceinline__ bool better(TS c, int i, const Best<TS> &b)
+{
+    return c < b.chi2 || (c == b.chi2 && i < b.idx);
+}
+
+// Load one seed and validate it.  0: live, 1: rejected (copied through),
+// 2: the float covariance is not positive definite (queue for the re-run).
+template <typename TS, typename TC, bool kQueueNotPD>
+__device__ __forceinline__ int load_track(const DevCfg<TS> &g, const MatchIO &io, int64_t i,
+                                          Trk<TS, TC> &T, int &grp)
+{
+    const int64_t n = io.n;
+    const TS *ip = reinterpret_cast<const TS *>(io.ip);
+    const TS *ic = reinterpret_cast<const TS *>(io.ic);
+    const TS *ix = reinterpret_cast<const TS *>(io.ix);
+    T.y = ip[i];
+    T.z = ip[n + i];
+    T.s = ip[2 * n + i];
+    T.t = ip[3 * n + i];
+    T.c = ip[4 * n + i];
+    T.x = ix[i];
+#pragma unroll
+    for (int k = 0; k < 15; k++) T.C[k] = TC(ic[k * n + i]);
+    T.sec = io.isec[i];
+    grp = io.igrp ? io.igrp[i] : 0;
+    bool bad = !(__builtin_isfinite(T.x) && T.sec >= 0 && T.sec < kSectors && grp >= 0 &&
+                 grp < g.bin.n_groups);
+    bad |= !(__builtin_isfinite(T.y) && __builtin_isfinite(T.z) && __builtin_isfinite(T.s) &&
+             __builtin_isfinite(T.t) && __builtin_isfinite(T.c));
+#pragma unroll
+    for (int k = 0; k < 15; k++) bad |= !__builtin_isfinite(T.C[k]);
+    if (!bad) bad = !(fabs(T.s) < g.snp_max);
+    if (!bad && !ldl_pd(T.C)) {
+        if (kQueueNotPD) return 2;  // positive definite in double is decided by the re-run
+        bad = true;
+    }
+    if (kQueueNotPD && io.force_fallback) return 2;
+    return bad ? 1 : 0;
+}
+
+// Propagation to the layer plane, sector hops, the layer's scattering.
+// False: the track stopped (status set).
+template <typename TS, typename TC>
+__device__ __forceinline__ bool predict(Trk<TS, TC> &T, int l, const DevCfg<TS> &g, uint32_t &status)
+{
+    const TS xl = g.x_layer[l];
+    if (!propagate(T, xl, g)) {
+        status |= kStopSnp;
+        return false;
+    }
+    for (int nrot = 0;; nrot++) {
+        if (fabs(T.y) <= xl * g.tan_half_sector) break;
+        if (nrot == 2) {
+            status |= kRotFail;
+            return false;
+        }
+        const bool up = T.y > TS(0);
+        if (!rotate(T, up, g)) {
+            status |= kRotFail;
+            return false;
+        }
+        T.sec = up ? (T.sec == kSectors - 1 ? 0 : T.sec + 1) : (T.sec == 0 ? kSectors - 1 : T.sec - 1);
+        if (!propagate(T, xl, g)) {
+            status |= kStopSnp;
+            return false;
+        }
+    }
+    add_ms(T, g);
+    return true;
+}
+
+// Covariance road at layer l.  False: nothing to search (out of the
+// chambers in z, or no positive definite innovation covariance).
+template <typename TS, typename TC>
+__device__ __forceinline__ bool open_road(const Trk<TS, TC> &T, int l, int grp, const DevCfg<TS> &g,
+                                          uint32_t &status, Road<TS> &R)
+{
+    const TS tau = g.tilt[l];
+    const TS f = sqrt(TS(1) - T.s * T.s);
+    R.y = T.y;
+    R.z = T.z;
+    R.tau = tau;
+    R.tphi = T.s / f;
+    R.tz = T.t / f;
+    const TS sy = poly2(g.sigma_y, T.s);
+    const TC vy = TC(sy) * TC(sy);
+    const TC Syy = T.C[YY] + TC(2) * TC(tau) * T.C[YZ] + TC(tau) * TC(tau) * T.C[ZZ] + vy;
+    const TC Syz = T.C[YZ] + TC(tau) * T.C[ZZ];
+    const TC Szz = T.C[ZZ] + TC(g.vz);
+    const TC det = Syy * Szz - Syz * Syz;
+    R.glo = 1;
+    R.ghi = 0;
+    if (!(Syy > TC(0) && Szz > TC(0) && det > TC(0))) {
+        status |= kNotPD;
+        return false;
+    }
+    R.si00 = TS(Szz / det);
+    R.si01 = TS(-Syz / det);
+    R.si11 = TS(Syy / det);
+    R.Ry = g.n_sigma_road * TS(sqrt(Syy));
+    R.Rz = g.n_sigma_road * TS(sqrt(Szz));
+    R.dytrk = g.drift_len * (R.tphi - g.tan_psi);
+    const TS sdy = poly2(g.sigma_dy, T.s);
+    const TS f3 = f * f * f;
+    R.gdy = g.n_sigma_dy *
+            TS(sqrt(TC(sdy) * TC(sdy) + TC(g.drift_len) * TC(g.drift_len) * T.C[SS] / (TC(f3) * TC(f3))));
+    const TS mz = g.dx_max * fabs(R.tz);
+    if (T.z + R.Rz + mz < g.z_min || T.z - R.Rz - mz > g.z_max) {
+        status |= kOutOfZ;
+        return false;
+    }
+    // cells overlapping the road; the slack keeps the set a superset of the
+    // gate's acceptance under rounding
+    const TS slack_y = TS(1e-3) + TS(1e-5) * R.Ry, slack_z = TS(1e-3) + TS(1e-5) * R.Rz;
+    const TS my = fabs(tau) * (R.Rz + mz + slack_z) + g.dx_max * fabs(R.tphi);
+    const int nrt = kStacks * g.bin.n_rows;
+    R.glo = zrow(T.z - R.Rz - mz - slack_z, g, nrt);
+    R.ghi = zrow(T.z + R.Rz + mz + slack_z, g, nrt);
+    R.yb0 = ybin((double)(T.y - R.Ry - my - slack_y), g.bin);
+    R.yb1 = ybin((double)(T.y + R.Ry + my + slack_y), g.bin);
+    R.sdet0 = T.sec * (kStacks * kLayers) + l;
+    R.gdet0 = grp * kDet + R.sdet0;
+    return true;
+}
+
+// Gates of one candidate record; chi2 valid when *pass.
+template <typename TS>
+__device__ __forceinline__ TS cand_chi2(const Road<TS> &R, TS ye, TS ze, const float4 &r, TS chi2_max,
+                                        bool &pass)
+{
+    const TS ddy = TS(r.y) - R.dytrk;
+    const TS zj = TS(r.z);
+    const TS rz = zj - ze;
+    const TS ry = TS(r.x) - (ye + R.tau * (ze - zj));
+    const TS chi2 = R.si00 * ry * ry + TS(2) * R.si01 * ry * rz + R.si11 * rz * rz;
+    pass = fabs(ddy) <= R.gdy && fabs(rz) <= R.Rz && fabs(ry) <= R.Ry && chi2 <= chi2_max;
+    return chi2;
+}
+
+// Scan of the road's cells by the G lanes of a group (G = 1: a lone lane).
+// Lane `sub` of the group first fetches the cell range of one pad row, so
+// the ranges of up to G rows arrive in one memory round trip; each range is
+// then broadcast and scanned with kUnroll independent record loads in flight
+// per lane.
+template <int G, typename TS>
+__device__ __forceinline__ void scan_road(const Road<TS> &R, int sub, const DevCfg<TS> &g,
+                                          const MatchIO &io, Best<TS> &B)
+{
+    constexpr int kUnroll = 4;
+    const int nr = g.bin.n_rows;
+    const uint32_t nyb = (uint32_t)g.bin.n_yb;
+    const bool misaligned = g.dx_max != TS(0);
+    for (int c0 = R.glo; c0 <= R.ghi; c0 += G) {
+        uint32_t a_l = 0, b_l = 0;
+        const int gl = c0 + sub;
+        if (gl <= R.ghi) {
+            const int st = gl / nr, rw = gl - st * nr;
+            const uint32_t base = ((uint32_t)(R.gdet0 + st * kLayers) * (uint32_t)nr + (uint32_t)rw) * nyb;
+            a_l = io.offsets[base + R.yb0];
+            b_l = io.offsets[base + R.yb1 + 1];
+        }
+        const int nrow = R.ghi - c0 + 1 < G ? R.ghi - c0 + 1 : G;
+        for (int j = 0; j < nrow; j++) {
+            const uint32_t a = G == 1 ? a_l : (uint32_t)__shfl((int)a_l, j, G);
+            const uint32_t b = G == 1 ? b_l : (uint32_t)__shfl((int)b_l, j, G);
+            const int st = (c0 + j) / nr;
+            TS ye = R.y, ze = R.z;
+            if (misaligned) {
+                const TS dxd = g.dx[R.sdet0 + st * kLayers];
+                ye = R.y + dxd * R.tphi;
+                ze = R.z + dxd * R.tz;
+            }
+            for (uint32_t k0 = a + (uint32_t)sub; k0 < b; k0 += G * kUnroll) {
+                float4 rec[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    const uint32_t k = k0 + (uint32_t)(u * G);
+                    if (k < b) rec[u] = io.sorted[k];
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    const uint32_t k = k0 + (uint32_t)(u * G);
+                    if (k < b) {
+                        bool pass;
+                        const TS c = cand_chi2(R, ye, ze, rec[u], g.chi2_max, pass);
+                        const int oj = __float_as_int(rec[u].w);
+                        const bool take = pass && better(c, oj, B);
+                        B.chi2 = take ? c : B.chi2;
+                        B.idx = take ? oj : B.idx;
+                        B.pos = take ? (int)k : B.pos;
+                        B.stack = take ? st : B.stack;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Per-track results accumulated over the layers (the per-layer index and
+// chi2 go straight to the output arrays).
+template <typename TS>
+struct Acc {
+    int nmatch;
+    TS chi2sum;
+    int lidx;   // this layer's match, -1 if none
+    TS lchi;    // its chi2
+};
+
+// Precise propagation to the winner's radius and the Kalman update.
+// 0: matched, 1: the track stopped, 2: covariance lost positive definiteness
+// (the update is kept and NOT_PD set unless the caller re-runs the track).
+template <typename TS, typename TC>
+__device__ __forceinline__ int apply_best(Trk<TS, TC> &T, int l, const Road<TS> &R, const Best<TS> &B,
+                                          const DevCfg<TS> &g, const MatchIO &io, uint32_t &status,
+                                          Acc<TS> &acc)
+{
+    const float4 r = io.sorted[B.pos];
+    const TS yj = TS(r.x), zj = TS(r.z);
+    const TS bdx = g.dx[R.sdet0 + B.stack * kLayers];
+    if (bdx != TS(0)) {
+        if (!propagate(T, g.x_layer[l] + bdx, g)) {
+            status |= kStopSnp;
+            return 1;
+        }
+    }
+    const TS ry = yj - (T.y + R.tau * (T.z - zj));
+    const TS rz = zj - T.z;
+    const TS syu = poly2(g.sigma_y, T.s);
+    int rc = 0;
+    if (!kalman_update(T, ry, rz, R.tau, TC(syu) * TC(syu), TC(g.vz))) {
+        status |= kNotPD;
+        rc = 2;
+    }
+    acc.lidx = B.idx;
+    acc.nmatch++;
+    acc.chi2sum += B.chi2;
+    acc.lchi = B.chi2;
+    if (!(fabs(T.s) < g.snp_max)) {
+        status |= kStopSnp;
+        return rc == 2 ? 2 : 1;
+    }
+    return rc;
+}
+
+template <typename TS>
+__device__ __forceinline__ void write_layer(const MatchIO &io, int64_t i, int l, const Acc<TS> &acc)
+{
+    io.oidx[l * io.n + i] = acc.lidx;
+    if (io.ochi2l) reinterpret_cast<TS *>(io.ochi2l)[l * io.n + i] = acc.lchi;
+}
+
+template <typename TS, typename TC>
+__device__ __forceinline__ void write_track(const MatchIO &io, int64_t i, const Trk<TS, TC> &T,
+                                            const Acc<TS> &acc, uint32_t status)
+{
+    const int64_t n = io.n;
+    TS *op = reinterpret_cast<TS *>(io.op);
+    TS *oc = reinterpret_cast<TS *>(io.oc);
+    TS *ox = reinterpret_cast<TS *>(io.ox);
+    TS *och = reinterpret_cast<TS *>(io.ochi2);
+    op[i] = T.y;
+    op[n + i] = T.z;
+    op[2 * n + i] = T.s;
+    op[3 * n + i] = T.t;
+    op[4 * n + i] = T.c;
+#pragma unroll
+    for (int k = 0; k < 15; k++) oc[k * n + i] = TS(T.C[k]);
+    ox[i] = T.x;
+    io.osec[i] = T.sec;
+    och[i] = acc.chi2sum;
+    io.onm[i] = acc.nmatch;
+    io.ost[i] = status;
+}
+
+template <typename TS> __device__ __forceinline__ void acc_init(Acc<TS> &acc)
+{
+    acc.nmatch = 0;
+    acc.chi2sum = TS(0);
+    acc.lidx = -1;
+    acc.lchi = TS(0);
+}
+
+// One track, one lane, start to end.  Returns false if the track must be
+// re-run with a double covariance (kQueueNotPD only).
+template <typename TS, typename TC, bool kQueueNotPD>
+__device__ __forceinline__ bool match_lane(const DevCfg<TS> &g, const MatchIO &io, int64_t i,
+                                           uint32_t status)
+{
+    Trk<TS, TC> T;
+    int grp;
+    const int ld = load_track<TS, TC, kQueueNotPD>(g, io, i, T, grp);
+    if (ld == 2) return false;
+    Acc<TS> acc;
+    acc_init(acc);
+    bool live = ld == 0;
+    if (ld == 1) status |= kBadInput;
+    for (int l = 0; l < kLayers; l++) {
+        acc.lidx = -1;
+        acc.lchi = TS(0);
+        Road<TS> R;
+        if (live && !predict(T, l, g, status)) live = false;
+        if (live && open_road(T, l, grp, g, status, R)) {
+            Best<TS> B = no_best<TS>();
+            scan_road<1>(R, 0, g, io, B);
+            if (B.idx != 0x7fffffff) {
+                const int rc = apply_best(T, l, R, B, g, io, status, acc);
+                if (rc == 2 && kQueueNotPD) return false;
+                if (rc != 0 && (status & kStopSnp)) live = false;
+            }
+        }
+        write_layer(io, i, l, acc);
+    }
+    write_track(io, i, T, acc, status);
+    return true;
+}
+
+// One lane per track (the plain kernel; double precision runs here).
+template <typename TS, typename TC, bool kFloatCov>
+__global__ void __launch_bounds__(256) k_match(DevCfg<TS> g, MatchIO io)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= io.n) return;
+    if (!match_lane<TS, TC, kFloatCov>(g, io, i, 0u))
+        io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
+}
+
+// Re-run of the queued tracks with a double covariance.  The last
+// workgroup to finish clears the queue for the next call.
+__global__ void __launch_bounds__(256) k_match_fallback(DevCfg<float> g, MatchIO io)
+{
+    const uint32_t cnt = *io.fb_count;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x)
+        match_lane<float, double, false>(g, io, io.fb_list[j], kFallback);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(io.fb_done, 1u) == gridDim.x - 1) {
+            atomicExch(io.fb_count, 0u);
+            atomicExch(io.fb_done, 0u);
+        }
+    }
+}
+
+// orders LDS traffic between the lanes of one wavefront
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Float state; the road scan of each track is shared by G lanes.  The
+// per-lane phases (propagation, scattering, road, update) stay one track per
+// lane; roads and winners pass through wave-private LDS slots.
+template <typename TC, int G, bool kFloatCov>
+__global__ void __launch_bounds__(256) k_match_coop(DevCfg<float> g, MatchIO io)
+{
+    __shared__ Road<float> roads[256];
+    __shared__ Best<float> bests[256];
+    const int tid = threadIdx.x, lane = tid & 63, wbase = tid & ~63;
+    const int sub = lane % G, gid = lane / G;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    Trk<float, TC> T;
+    int grp = 0;
+    uint32_t status = 0;
+    bool live = false, queued = false;
+    Acc<float> acc;
+    acc_init(acc);
+    if (i < io.n) {
+        const int ld = load_track<float, TC, kFloatCov>(g, io, i, T, grp);
+        live = ld == 0;
+        queued = ld == 2;
+        if (ld == 1) status |= kBadInput;
+    }
+    for (int l = 0; l < kLayers; l++) {
+        acc.lidx = -1;
+        acc.lchi = 0.0f;
+        Road<float> R;
+        R.glo = 1;
+        R.ghi = 0;
+        bool search = false;
+        if (live) {
+            if (!predict(T, l, g, status))
+                live = false;
+            else
+                search = open_road(T, l, grp, g, status, R);
+        }
+        roads[tid] = R;
+        wave_sync();
+#pragma unroll 1
+        for (int rnd = 0; rnd < G; rnd++) {
+            const int slot = wbase + rnd * (64 / G) + gid;
+            const Road<float> Q = roads[slot];
+            Best<float> B = no_best<float>();
+            if (Q.glo <= Q.ghi) scan_road<G>(Q, sub, g, io, B);
+#pragma unroll
+            for (int off = G / 2; off >= 1; off >>= 1) {
+                const float oc = __shfl_xor(B.chi2, off, 64);
+                const int oi = __shfl_xor(B.idx, off, 64);
+                const int op = __shfl_xor(B.pos, off, 64);
+                const int os = __shfl_xor(B.stack, off, 64);
+                const bool take = better(oc, oi, B);
+                B.chi2 = take ? oc : B.chi2;
+                B.idx = take ? oi : B.idx;
+                B.pos = take ? op : B.pos;
+                B.stack = take ? os : B.stack;
+            }
+            if (sub == 0) bests[slot] = B;
+        }
+        wave_sync();
+        if (search) {
+            const Best<float> B = bests[tid];
+            if (B.idx != 0x7fffffff) {
+                const int rc = apply_best(T, l, R, B, g, io, status, acc);
+                if (rc == 2 && kFloatCov) {
+                    queued = true;
+                    live = false;
+                } else if (rc != 0 && (status & kStopSnp)) {
+                    live = false;
+                }
+            }
+        }
+        if (i < io.n) write_layer(io, i, l, acc);
+    }
+    if (i < io.n) {
+        if (queued)
+            io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
+        else
+            write_track(io, i, T, acc, status);
+    }
+}
+
+template <typename TC, bool kFloatCov>
+void launch_coop(int lanes, const DevCfg<float> &gf, const MatchIO &io, unsigned grid, int block,
+                 hipStream_t s)
+{
+    switch (lanes) {
+    case 4: hipLaunchKernelGGL((k_match_coop<TC, 4, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
+    case 16: hipLaunchKernelGGL((k_match_coop<TC, 16, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
+    case 32: hipLaunchKernelGGL((k_match_coop<TC, 32, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
+    case 64: hipLaunchKernelGGL((k_match_coop<TC, 64, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
+    default: hipLaunchKernelGGL((k_match_coop<TC, 8, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
+    }
+}
+
+}  // namespace
+
+void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
+                  const MatchIO &io, int block, int lanes, hipStream_t s)
+{
+    if (io.n <= 0) return;
+    const unsigned grid = (unsigned)((io.n + block - 1) / block);
+    if (precision == 0) {
+        hipLaunchKernelGGL((k_match<double, double, false>), dim3(grid), dim3(block), 0, s, gd, io);
+    } else if (precision == 2) {
+        if (lanes == 1)
+            hipLaunchKernelGGL((k_match<float, double, false>), dim3(grid), dim3(block), 0, s, gf, io);
+        else
+            launch_coop<double, false>(lanes, gf, io, grid, block, s);
+    } else {
+        if (lanes == 1)
+            hipLaunchKernelGGL((k_match<float, float, true>), dim3(grid), dim3(block), 0, s, gf, io);
+        else
+            launch_coop<float, true>(lanes, gf, io, grid, block, s);
+        hipLaunchKernelGGL(k_match_fallback, dim3(64), dim3(256), 0, s, gf, io);
+    }
+}
+
+}  // namespace trd

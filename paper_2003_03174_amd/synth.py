@@ -329,10 +329,11 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
     drop = np.zeros((N_LAYERS, n), dtype=bool)
     if ineff_frac > 0:
         sel = np.nonzero(rng.random(n) < ineff_frac)[0]
-        nlost = np.where(rng.random(sel.size) < 0.5, 1, 2)
-        for i, k in zip(sel, nlost):
-            layers = rng.choice(N_LAYERS, size=k, replace=False)
-            drop[layers, i] = True
+        two = rng.random(sel.size) < 0.5
+        l1 = rng.integers(0, N_LAYERS, sel.size)
+        l2 = (l1 + rng.integers(1, N_LAYERS, sel.size)) % N_LAYERS   # a different layer
+        drop[l1, sel] = True
+        drop[l2[two], sel[two]] = True
 
     ys, zs, dys, dets, rows, labels, lays = [], [], [], [], [], [], []
     for l, tr in enumerate(tk_rows):

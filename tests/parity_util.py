@@ -1,0 +1,143 @@
+"""Element-by-element comparison of the HIP path's results with the FP64 oracle.
+
+Norms (relative errors with floors): y, z: 10 cm; sin phi, tan lambda: 0.1;
+q/pT: 0.1 c/GeV; covariance entries: |dC_ij| / sqrt(C_ii C_jj).
+
+Tolerances:
+  * double path: 1e-12 on state and covariance;
+  * float path: 1e-5 on the state; the float covariance is reported (its
+    Joseph-form update is bounded by positive definiteness, not by 1e-5) and
+    checked against a loose bound;
+  * chi2: the state tolerance carried through the residual,
+    |d chi2| <= 6 layers * 2 sqrt(chi2_max) / sigma_y * (tol * 10 cm).
+Index parity: a track whose oracle run holds a decision-margin flag is
+compared only on the layers before the first flagged layer (there, a
+different but correct rounding may legitimately pick another candidate).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FLOORS = np.array([10.0, 10.0, 0.1, 0.1, 0.1])
+DIAG = (0, 5, 9, 12, 14)
+GPU_ONLY_BITS = 8 | 16   # FP64_FALLBACK, NOT_PD
+
+STATE_TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_cov64": 1e-5}
+COV_TOL = {"fp64": 1e-12, "fp32": 5e-2, "fp32_cov64": 5e-2}
+
+# decision margins the oracle uses to flag tracks for each precision (the
+# absolute terms follow from the state tolerance: 1e-5 * 10 cm on y and z)
+MARGINS = {
+    "fp64": dict(margin_rel=1e-4),
+    "fp32": dict(margin_rel=1e-4, m_len=1e-3, m_dy=2e-4, m_chi2=2e-2, m_snp=1e-5),
+    "fp32_cov64": dict(margin_rel=1e-4, m_len=1e-3, m_dy=2e-4, m_chi2=2e-2, m_snp=1e-5),
+}
+
+
+def chi2_tol(prec, chi2_max=13.8155, sigma_y=0.04):
+    return 6 * 2 * math.sqrt(chi2_max) / sigma_y * STATE_TOL[prec] * 10.0
+
+
+@dataclass
+class Report:
+    prec: str
+    n: int = 0
+    n_flagged: int = 0
+    n_compared: int = 0
+    idx_mismatch: int = 0
+    idx_mismatch_flagged_prefix: int = 0
+    status_mismatch: int = 0
+    sector_mismatch: int = 0
+    nmatch_mismatch: int = 0
+    state_err: float = 0.0
+    state_err_by_comp: list = field(default_factory=list)
+    x_err: float = 0.0
+    cov_err: float = 0.0
+    chi2_err: float = 0.0
+    n_fallback: int = 0
+    bad_tracks: list = field(default_factory=list)
+
+    @property
+    def ok(self):
+        return (self.idx_mismatch == 0 and self.idx_mismatch_flagged_prefix == 0 and
+                self.status_mismatch == 0 and self.sector_mismatch == 0 and
+                self.nmatch_mismatch == 0 and self.state_err <= STATE_TOL[self.prec] and
+                self.x_err <= STATE_TOL[self.prec] and self.cov_err <= COV_TOL[self.prec] and
+                self.chi2_err <= chi2_tol(self.prec))
+
+    def summary(self):
+        return (f"{self.prec}: n={self.n} flagged={self.n_flagged} compared={self.n_compared} "
+                f"idx_mm={self.idx_mismatch}+{self.idx_mismatch_flagged_prefix} "
+                f"status_mm={self.status_mismatch} sec_mm={self.sector_mismatch} "
+                f"nm_mm={self.nmatch_mismatch} state={self.state_err:.3g} "
+                f"by_comp={[f'{v:.2g}' for v in self.state_err_by_comp]} x={self.x_err:.3g} "
+                f"cov={self.cov_err:.3g} chi2={self.chi2_err:.3g} fallback={self.n_fallback} "
+                f"ok={self.ok}")
+
+
+def compare(ref, got, prec, sel=None):
+    """ref: oracle.match output; got: numpy copies of the device results
+    (same keys).  sel: optional index array of tracks that `ref` covers
+    (ref holds len(sel) tracks, got holds all)."""
+    g = dict(got)
+    if sel is not None:
+        sel = np.asarray(sel)
+        for k in ("idx", "p", "cov", "chi2_layer"):
+            if g.get(k) is not None:
+                g[k] = g[k][:, sel]
+        for k in ("x", "sector", "chi2", "n_match", "status"):
+            g[k] = g[k][sel]
+    n = ref["x"].size
+    r = Report(prec=prec, n=n)
+    flagged = ref["flags"] != 0
+    fl = ref["flag_layer"]
+    r.n_flagged = int(flagged.sum())
+    gst = g["status"].astype(np.int64)
+    r.n_fallback = int(((gst & 8) != 0).sum())
+    # indices: all layers of unflagged tracks, the layers before the flag otherwise
+    layer = np.arange(6)[:, None]
+    cmp_mask = layer < fl[None, :]
+    mm = (g["idx"] != ref["idx"]) & cmp_mask
+    r.idx_mismatch = int(mm[:, ~flagged].any(axis=0).sum())
+    r.idx_mismatch_flagged_prefix = int(mm[:, flagged].any(axis=0).sum())
+    u = ~flagged
+    r.n_compared = int(u.sum())
+    st_g = (gst & ~GPU_ONLY_BITS)[u]
+    r.status_mismatch = int((st_g != ref["status"][u].astype(np.int64)).sum())
+    r.sector_mismatch = int((g["sector"][u] != ref["sector"][u]).sum())
+    r.nmatch_mismatch = int((g["n_match"][u] != ref["n_match"][u]).sum())
+    # rejected seeds are copied through (NaN included) on both sides
+    bad_in = (ref["status"] & 32) != 0
+    for k in ("p", "cov"):
+        if not np.array_equal(g[k][:, bad_in].astype(np.float64), ref[k][:, bad_in], equal_nan=True):
+            r.status_mismatch += 1
+    same = u & ~bad_in & (g["sector"] == ref["sector"]) & ((gst & ~GPU_ONLY_BITS) == ref["status"])
+    same &= np.all(g["idx"] == ref["idx"], axis=0)
+    if same.any():
+        gp, rp = g["p"][:, same].astype(np.float64), ref["p"][:, same]
+        e = np.abs(gp - rp) / np.maximum(np.abs(rp), FLOORS[:, None])
+        r.state_err_by_comp = [float(v) for v in e.max(axis=1)]
+        r.state_err = float(e.max())
+        r.x_err = float((np.abs(g["x"][same].astype(np.float64) - ref["x"][same]) /
+                         np.maximum(np.abs(ref["x"][same]), 1.0)).max())
+        gc, rc = g["cov"][:, same].astype(np.float64), ref["cov"][:, same]
+        k = 0
+        worst = 0.0
+        for i in range(5):
+            for j in range(i, 5):
+                den = np.sqrt(rc[DIAG[i]] * rc[DIAG[j]])
+                worst = max(worst, float((np.abs(gc[k] - rc[k]) / den).max()))
+                k += 1
+        r.cov_err = worst
+        r.chi2_err = float(np.abs(g["chi2"][same].astype(np.float64) - ref["chi2"][same]).max())
+        if r.state_err > STATE_TOL[prec]:
+            bad = np.nonzero(same)[0][np.argsort(-e.max(axis=0))[:5]]
+            r.bad_tracks = [int(b) for b in bad]
+    return r
+
+
+def to_numpy(out):
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}

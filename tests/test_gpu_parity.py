@@ -1,0 +1,243 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Sizes: 1,000-track and 20,000-track frames (several workgroups, ragged tails),
+multi-frame batches, and the full 450,000-track distortion batch in the
+launch configuration the benchmark times (sampled tracks against the
+oracle, binning compared in full).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2003_03174_amd import binding as B
+from paper_2003_03174_amd import synth
+from tests import parity_util as pu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def workload(name, **kw):
+    key = (name, tuple(sorted((k, str(v)) for k, v in kw.items())))
+    if key not in _cache:
+        _cache[key] = synth.generate(name, **kw) if name else synth.generate(**kw)
+    return _cache[key]
+
+
+def run_gpu(w, prec, block_size=0, params=None, search_lanes=0):
+    P = params or w["params"]
+    lay = synth.to_device_layout(w)
+    d = B.device_inputs(lay, prec)
+    m = B.Matcher(P, prec, block_size=block_size, search_lanes=search_lanes)
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+    out = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    torch.cuda.synchronize()
+    res = pu.to_numpy(out)
+    off, srt = m.binning()
+    torch.cuda.synchronize()
+    res["offsets"] = off.cpu().numpy().view(np.uint32)
+    res["sorted"] = srt.cpu().numpy()
+    m.close()
+    return res
+
+
+def check_binning(w, res):
+    perm, off = O.bin_tracklets(w["params"], w)
+    assert np.array_equal(res["offsets"], off), "cell offsets differ"
+    nv = int(off[-1])
+    srt = res["sorted"][:nv]
+    gidx = srt[:, 3].copy().view(np.int32)
+    assert np.array_equal(gidx, perm[:nv]), "sorted permutation differs"
+    assert np.array_equal(srt[:, 0], w["tkl_y"][gidx].astype(np.float32))
+    assert np.array_equal(srt[:, 1], w["tkl_dy"][gidx].astype(np.float32))
+    assert np.array_equal(srt[:, 2], w["tkl_z"][gidx].astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
+def test_small_frame(prec):
+    w = workload("c1_small_fp64")
+    res = run_gpu(w, prec)
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
+    rep = pu.compare(ref, res, prec)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tilted_pads_and_misaligned_chambers(prec):
+    rng = np.random.default_rng(7)
+    params = dict(y_bin_w=4.0, n_yb=32, tilt=synth.tilt_pm2deg(), dx_chamber=rng.uniform(-0.5, 0.5, 540))
+    w = workload(None, n_tracks=3000, seed=17, fake_ratio=0.5, ineff_frac=0.1, params=params)
+    res = run_gpu(w, prec)
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
+    rep = pu.compare(ref, res, prec)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
+def test_frame_20k(prec):
+    w = workload("c2_frame_20k")
+    res = run_gpu(w, prec)
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
+    rep = pu.compare(ref, res, prec)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
+def test_multi_frame_groups():
+    w = synth.generate_frames(2, 6, [500, 3000, 1, 2500, 800, 1200], [0.2, 0.8, 0.5, 0.3, 0.6, 0.4],
+                              params_over=dict(y_bin_w=8.0, n_yb=16), ineff_frac=0.1)
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
+    m = res["idx"] >= 0
+    assert np.array_equal(w["tkl_group"][res["idx"][m]], np.broadcast_to(w["group"], m.shape)[m])
+
+
+def test_distortion_batch_full_size_sampled():
+    """450k tracks / ~3.8M tracklets, float path with block 256 as timed:
+    binning bit-exact in full, 3000 sampled tracks against the oracle."""
+    w = workload("c5_distortion_450k")
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    sel = np.random.default_rng(0).choice(w["n_tracks"], 3000, replace=False)
+    sel.sort()
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"], track_slice=sel)
+    rep = pu.compare(ref, res, "fp32", sel=sel)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+    # whole-batch properties: every match is a tracklet of the right layer/sector
+    idx = res["idx"]
+    m = idx >= 0
+    lay = np.broadcast_to(np.arange(6)[:, None], idx.shape)
+    assert np.array_equal(w["tkl_layer"][idx[m]], lay[m])
+
+
+def test_fp64_full_size_sampled():
+    w = workload("c5_distortion_450k")
+    res = run_gpu(w, "fp64")
+    sel = np.random.default_rng(1).choice(w["n_tracks"], 1500, replace=False)
+    sel.sort()
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp64"], track_slice=sel)
+    rep = pu.compare(ref, res, "fp64", sel=sel)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
+def test_forced_fallback_equals_double_covariance_path():
+    """Test hook: every track takes the re-run; the result must be bit-identical
+    to the float-state / double-covariance path (same arithmetic)."""
+    w = workload("c2_frame_20k")
+    P = w["params"]
+    lay = synth.to_device_layout(w)
+    d = B.device_inputs(lay, "fp32")
+    outs = []
+    for prec, flags in (("fp32", B.TRD_CFG_FORCE_FALLBACK), ("fp32_cov64", 0)):
+        m = B.Matcher(P, prec, flags=flags)
+        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+        outs.append(pu.to_numpy(m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])))
+        torch.cuda.synchronize()
+        m.close()
+    a, b = outs
+    assert np.all(a["status"] & B.TRK_FP64_FALLBACK)
+    assert np.array_equal(a["status"] & ~B.TRK_FP64_FALLBACK, b["status"])
+    for k in ("idx", "p", "cov", "x", "sector", "chi2", "n_match"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_fallback_for_seeds_singular_in_float():
+    """Seeds whose y-z covariance block [[3, 1], [1, fl32(1/3)]] is positive
+    definite in double but singular in float: the float path must hand them to
+    the double-covariance re-run, whose result agrees with the oracle."""
+    w = dict(workload("c1_small_fp64"))
+    w["cov"] = w["cov"].copy()
+    sel = np.arange(0, w["n_tracks"], 10)
+    w["cov"][0, sel] = 3.0
+    w["cov"][1, sel] = 1.0
+    w["cov"][5, sel] = float(np.float32(1.0 / 3.0))
+    assert O.ldl_pd(w["cov"][:, sel[0]])
+    res = run_gpu(w, "fp32")
+    st = res["status"].astype(np.int64)
+    fb = np.nonzero((st & B.TRK_FP64_FALLBACK) != 0)[0]
+    assert set(fb.tolist()) == set(sel.tolist()), (fb.size, sel.size)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32_cov64"])
+    rep = pu.compare(ref, res, "fp32_cov64")
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
+def test_empty_and_single():
+    w = workload("c1_small_fp64")
+    w0 = dict(w)
+    for k in ("tkl_y", "tkl_z", "tkl_dy"):
+        w0[k] = np.zeros(0)
+    w0["tkl_det_row"] = np.zeros(0, np.uint32)
+    w0["tkl_group"] = np.zeros(0, np.int32)
+    res = run_gpu(w0, "fp32")
+    assert np.all(res["idx"] == -1) and np.all(res["n_match"] == 0)
+    ref = O.match(w0["params"], w0, threads=0, margins=pu.MARGINS["fp32"])
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
+    w1 = dict(w)
+    for k in ("p", "cov"):
+        w1[k] = np.ascontiguousarray(w[k][:, 5:6])
+    for k in ("x", "sector", "group"):
+        w1[k] = np.ascontiguousarray(w[k][5:6])
+    w1["n_tracks"] = 1
+    res = run_gpu(w1, "fp64")
+    ref = O.match(w1["params"], w1, threads=0)
+    assert pu.compare(ref, res, "fp64").ok
+
+
+def test_invalid_tracklets_and_bad_seeds():
+    w = dict(workload("c1_small_fp64"))
+    w["tkl_det_row"] = w["tkl_det_row"].copy()
+    w["tkl_y"] = w["tkl_y"].copy()
+    w["tkl_det_row"][3] = (541 << 5) | 2
+    w["tkl_det_row"][4] = (10 << 5) | 25
+    w["tkl_y"][5] = np.nan
+    w["p"] = w["p"].copy()
+    w["sector"] = w["sector"].copy()
+    w["p"][0, 0] = np.nan
+    w["sector"][1] = 99
+    w["p"][2, 2] = float(np.float32(0.97))
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    assert res["offsets"][-1] == w["n_tracklets"] - 3
+    st = res["status"]
+    for i in (0, 1, 2):
+        assert st[i] & B.TRK_BAD_INPUT and res["n_match"][i] == 0
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    assert np.all(ref["status"][:3] == B.TRK_BAD_INPUT)
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
+
+
+def test_deterministic_repeats():
+    w = workload("c2_frame_20k")
+    a = run_gpu(w, "fp32")
+    b = run_gpu(w, "fp32")
+    for k in ("idx", "p", "cov", "chi2", "status", "offsets", "sorted"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_cov64"])
+def test_launch_shapes_agree(prec):
+    """Block size and lanes per track change the schedule, not the arithmetic:
+    results are bit-identical across launch shapes."""
+    w = workload("c2_frame_20k")
+    base = run_gpu(w, prec, block_size=256, search_lanes=1)
+    for bs, lanes in ((64, 4), (128, 8), (256, 16), (192, 32), (256, 64)):
+        o = run_gpu(w, prec, block_size=bs, search_lanes=lanes)
+        for k in ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status"):
+            assert np.array_equal(o[k], base[k], equal_nan=True), (bs, lanes, k)
