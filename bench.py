@@ -39,26 +39,49 @@ def bin_alg_bytes(n_tkl, n_cells):
     return n_tkl * (20 + 20 + 16) + n_cells * 16
 
 
-def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0):
+def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None):
     import torch
     from paper_2003_03174_amd import binding as B
     from paper_2003_03174_amd import synth
 
-    lay = synth.to_device_layout(w)
-    d = B.device_inputs(lay, prec)
+    if d is None:
+        d = B.device_inputs(synth.to_device_layout(w), prec)
     n = w["n_tracks"]
     m = B.Matcher(w["params"], prec, block_size=block_size, search_lanes=search_lanes)
     m.reserve(w["n_tracklets"], w["n_groups"], n)
     out = m.alloc_results(n, chi2_layer=False)
     stream = torch.cuda.current_stream()
 
+    def body():
+        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+
+    g = None
+    if graph:
+        # bin + match of the whole batch captured once, replayed per step
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            body()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            body()
+        torch.cuda.synchronize()
+
     def step(evs=None):
         if evs:
             evs[0].record(stream)
-        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
-        if evs:
-            evs[1].record(stream)
-        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+        if g is not None:
+            g.replay()
+            if evs:
+                evs[1].record(stream)
+        else:
+            m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+            if evs:
+                evs[1].record(stream)
+            m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
         if evs:
             evs[2].record(stream)
 
@@ -129,6 +152,8 @@ def main():
     ap.add_argument("--search-lanes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
+    ap.add_argument("--graph", action="store_true", help="replay bin + match as one captured graph")
+    ap.add_argument("--autotune", action="store_true", help="pick block size and lanes per track first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -151,12 +176,21 @@ def main():
         log("calibration copy: 3 x 512 MiB read + 512 MiB written")
         del src, dst
     log(f"generating {args.workload}")
-    w = synth.generate(args.workload)
+    w = synth.load_workload(args.workload)
     P = w["params"]
     n, ntk, ng = w["n_tracks"], w["n_tracklets"], w["n_groups"]
     n_cells = ng * 540 * P["n_rows"] * P["n_yb"]
     log(f"{n} tracks, {ntk} tracklets, {n_cells} cells; timing {args.precision}")
-    r = run_gpu(w, args.precision, args.steps, args.warmup, args.block_size, args.search_lanes)
+    tuned = None
+    if args.autotune:
+        from paper_2003_03174_amd import autotune, binding
+        d = binding.device_inputs(synth.to_device_layout(w), args.precision)
+        tuned = autotune.tune(P, d, ng, args.precision, use_cache=False)
+        args.block_size, args.search_lanes = tuned["block_size"], tuned["search_lanes"]
+        log(f"autotuned: block {args.block_size}, lanes {args.search_lanes} ({tuned['ms']:.3f} ms)")
+        del d
+    r = run_gpu(w, args.precision, args.steps, args.warmup, args.block_size, args.search_lanes,
+                graph=args.graph)
     ms = r["wall_ms_per_step"]
     match_avg = sum(r["match_ms"]) / len(r["match_ms"])
     bin_avg = sum(r["bin_ms"]) / len(r["bin_ms"])
@@ -177,9 +211,9 @@ def main():
         "dtype": "f32" if args.precision != "fp64" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{args.workload}: {n} seed tracks, {ntk} tracklets (50% fakes), "
-                         f"pT^-3 above 0.3 GeV/c, 5-15 cm seed distortion, road 3 sigma, "
-                         f"{n_cells} cells (2 cm y bins)"),
+            "workload": f"{args.workload}: {n} seed tracks, {ntk} tracklets, {ng} group(s); "
+                        + synth.describe(args.workload) + f"; {n_cells} cells",
+            "graph": bool(args.graph),
             "precision": args.precision,
             "block_size": args.block_size or 256,
             "search_lanes": args.search_lanes or 8,
@@ -189,6 +223,7 @@ def main():
                        "bin_avg": bin_avg, "match_avg": match_avg},
         "tracks_ge2_matches_per_s": r["n_ge2"] / (ms * 1e-3),
         "fp64_fallback_tracks": r["n_fallback"],
+        "autotune": tuned["table"] if tuned else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_match (trd_match)", "alg_bytes_per_launch": ab},

@@ -84,9 +84,12 @@ typedef struct trd_config {
     double z_min;             /* lower z edge of stack 0; chambers span [z_min, -z_min] */
     double pad_len;           /* pad-row length in z */
     int32_t n_rows;           /* pad rows per stack (<= 32) */
-    int32_t n_yb;             /* y bins per pad row in the tracklet cells */
+    int32_t n_yb;             /* y bins per (pad row, dy bin) in the tracklet cells */
+    int32_t n_db;             /* deflection (dy) bins per pad row; 1 = no dy binning */
+    uint32_t flags;           /* TRD_CFG_* */
     double y_bin_w;           /* y bin width, a power of two; bins cover
                                  [-n_yb*w/2, n_yb*w/2), outer bins are open */
+    double dy_bin_w;          /* dy bin width, a power of two, same layout */
     double drift_len;         /* drift length L: dy = L * (tan phi - tan_psi) */
     double dx_chamber[540];   /* radial offset of each chamber from x_layer (misalignment) */
     double bz;                /* solenoid field */
@@ -101,10 +104,9 @@ typedef struct trd_config {
     double snp_max;           /* stop when |sin phi| reaches this */
     uint64_t hbm_budget_bytes;/* cap on the context's device memory, 0 = none */
     int32_t block_size;       /* match workgroup size: 64, 128, 192 or 256; 0 = 256 */
-    int32_t search_lanes;     /* float paths: lanes that scan one track's road together:
-                                 1 (one lane per track), 4, 8, 16, 32 or 64; 0 = 8 */
-    uint32_t flags;           /* TRD_CFG_* */
-    uint32_t reserved;        /* must be 0 */
+    int32_t search_lanes;     /* float paths: lanes that share one track's road (each
+                                 scans whole cell ranges): 1 (one lane per track),
+                                 4, 8, 16, 32 or 64; 0 = 8 */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */
@@ -144,7 +146,7 @@ typedef struct trd_binning_view {
                                 offsets[n_cells] = number of valid tracklets */
     const float *sorted;     /* [n_valid][4]: y, dy, z, input index (int32 bits),
                                 ordered by (cell, input index) */
-    int64_t n_cells;         /* n_groups * 540 * n_rows * n_yb */
+    int64_t n_cells;         /* n_groups * 540 * n_rows * n_db * n_yb */
     int64_t n_tracklets;     /* tracklets passed to the last load */
 } trd_binning_view;
 
@@ -159,8 +161,10 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out);
  * Errors: TRD_EINVAL, TRD_ENOMEM, TRD_EBUDGET. */
 int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t max_tracks);
 
-/* Bins the tracklets into (group, chamber, pad row, y bin) cells: exact
- * cell keys, counts, exclusive scan and a stable scatter into ctx-owned
+/* Bins the tracklets into (group, chamber, pad row, dy bin, y bin) cells
+ * (y bins innermost, so the cells of one (row, dy bin) that overlap a road
+ * are contiguous): exact cell keys, counts, exclusive scan and a stable
+ * scatter into ctx-owned
  * sorted storage.  The caller may reuse `t`'s buffers once the stream has
  * passed this call.  Tracklets with a det >= 540, a row >= n_rows, a group
  * outside [0, n_groups) or a non-finite value are dropped.

@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trd_oracle.c")
-_LIB = os.path.join(_HERE, "libtrd_oracle.so")
+_LIB = os.environ.get("TRD_ORACLE_LIB") or os.path.join(_HERE, "libtrd_oracle.so")
 
 ST_STOP_SNP, ST_ROT_FAIL, ST_OUT_OF_Z, ST_BAD_INPUT = 1, 2, 4, 32
 FL_P1, FL_P2, FL_P3, FL_P4 = 1, 2, 4, 8
@@ -26,7 +26,7 @@ class OCfg(C.Structure):
         ("x_layer", C.c_double * 6),
         ("tilt", C.c_double * 6),
         ("z_min", C.c_double), ("pad_len", C.c_double),
-        ("y_bin_w", C.c_double), ("drift_len", C.c_double),
+        ("y_bin_w", C.c_double), ("dy_bin_w", C.c_double), ("drift_len", C.c_double),
         ("dx_chamber", C.c_double * 540),
         ("bz", C.c_double), ("x_over_x0", C.c_double), ("mass", C.c_double),
         ("sigma_y", C.c_double * 3), ("sigma_dy", C.c_double * 3), ("tan_psi", C.c_double),
@@ -34,12 +34,16 @@ class OCfg(C.Structure):
         ("snp_max", C.c_double),
         ("m_rel", C.c_double), ("m_len", C.c_double), ("m_dy", C.c_double),
         ("m_chi2", C.c_double), ("m_snp", C.c_double),
-        ("n_rows", C.c_int32), ("n_yb", C.c_int32),
+        ("n_rows", C.c_int32), ("n_yb", C.c_int32), ("n_db", C.c_int32),
     ]
 
 
 def build(force=False):
-    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP).  A library
+    named by TRD_ORACLE_LIB (a planted-mistake variant in a check of the
+    pins) is used as it is."""
+    if os.environ.get("TRD_ORACLE_LIB"):
+        return _LIB
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp"
@@ -86,6 +90,7 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
         c.tilt[l] = P["tilt"][l]
     c.z_min, c.pad_len = P["z_min"], P["pad_len"]
     c.y_bin_w, c.drift_len = P["y_bin_w"], P["drift_len"]
+    c.dy_bin_w, c.n_db = P["dy_bin_w"], P["n_db"]
     for d in range(540):
         c.dx_chamber[d] = float(P["dx_chamber"][d])
     c.bz, c.x_over_x0, c.mass = P["bz"], P["x_over_x0"], P["mass"]
@@ -114,7 +119,7 @@ def bin_tracklets(params, w):
     cfg = make_cfg(params)
     n = int(w["tkl_y"].size)
     ng = int(w.get("n_groups", 1))
-    nc = ng * 540 * params["n_rows"] * params["n_yb"]
+    nc = ng * 540 * params["n_rows"] * params["n_db"] * params["n_yb"]
     y, z, dy = _f64(w["tkl_y"]), _f64(w["tkl_z"]), _f64(w["tkl_dy"])
     dr = np.ascontiguousarray(w["tkl_det_row"], dtype=np.uint32)
     g = np.ascontiguousarray(w["tkl_group"], dtype=np.int32) if "tkl_group" in w else None

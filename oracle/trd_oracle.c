@@ -32,8 +32,10 @@
  *     gate width adds the track slope error: sqrt(s_dy^2 + L^2 C_ss / f^6);
  *   - road half widths n_road * sqrt(S_yy), n_road * sqrt(S_zz) around the
  *     prediction; chi2 <= chi2_max; winner = lexicographic min (chi2, index);
- *   - tracklet cells: key = ((group*540 + det)*n_rows + row)*n_yb + ybin,
- *     ybin = clamp(floor((y - y_min) * (1/w)), 0, n_yb-1) in double.
+ *   - tracklet cells: key = (((group*540 + det)*n_rows + row)*n_db + dbin)*n_yb
+ *     + ybin, ybin = clamp(floor((y - y_min) * (1/w)), 0, n_yb-1) and dbin the
+ *     same on dy with its own width, both in double; a road is searched over
+ *     the pad rows x deflection bins x y bins that overlap it.
  *
  * Decision-margin flags mark tracks where a gate, tie or geometric decision
  * lies within a margin, so that a correct implementation in a different
@@ -68,13 +70,14 @@ typedef struct {
     double tilt[NLAY];          /* tan of the pad tilt angle per layer */
     double z_min, pad_len;
     double y_bin_w;             /* power of two, cm */
+    double dy_bin_w;            /* power of two, cm (deflection bins) */
     double drift_len;
     double dx_chamber[NDET];
     double bz, x_over_x0, mass;
     double sigma_y[3], sigma_dy[3], tan_psi;
     double chi2_max, n_sigma_dy, n_sigma_road, snp_max;
     double m_rel, m_len, m_dy, m_chi2, m_snp; /* decision margins */
-    int32_t n_rows, n_yb;
+    int32_t n_rows, n_yb, n_db;
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -332,17 +335,21 @@ static double poly2(const double a[3], double s) { return a[0] + a[1] * s + a[2]
 
 static int64_t n_cells_of(const ocfg *g, int32_t n_groups)
 {
-    return (int64_t)n_groups * NDET * g->n_rows * g->n_yb;
+    return (int64_t)n_groups * NDET * g->n_rows * g->n_db * g->n_yb;
 }
 
-static int ybin_of(const ocfg *g, double y)
+/* bin of v among n bins of width w centred on 0, outer bins open */
+static int bin_of(double v, double w, int n)
 {
-    double ymin = -g->y_bin_w * g->n_yb / 2.0;
-    double u = floor((y - ymin) * (1.0 / g->y_bin_w));
-    if (u < 0) return 0;
-    if (u > g->n_yb - 1) return g->n_yb - 1;
+    double lo = -w * n / 2.0;
+    double u = floor((v - lo) * (1.0 / w));
+    if (!(u >= 0)) return 0;
+    if (u > n - 1) return n - 1;
     return (int)u;
 }
+
+static int ybin_of(const ocfg *g, double y) { return bin_of(y, g->y_bin_w, g->n_yb); }
+static int dbin_of(const ocfg *g, double dy) { return bin_of(dy, g->dy_bin_w, g->n_db); }
 
 /* Cell key of one tracklet; the invalid ones get n_cells (placed last). */
 static int64_t tkl_key(const ocfg *g, double y, double z, double dy, uint32_t det_row,
@@ -352,7 +359,8 @@ static int64_t tkl_key(const ocfg *g, double y, double z, double dy, uint32_t de
     if (det >= NDET || (int32_t)row >= g->n_rows || grp < 0 || grp >= n_groups ||
         !isfinite(y) || !isfinite(z) || !isfinite(dy))
         return n_cells_of(g, n_groups);
-    return (((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_yb + ybin_of(g, y);
+    return ((((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_db + dbin_of(g, dy)) * g->n_yb +
+           ybin_of(g, y);
 }
 
 typedef struct { int64_t key; int64_t idx; } keyidx;
@@ -484,6 +492,7 @@ static void gather_candidates(const ocfg *g, const otkl *T, const road_t *r, int
      * cover misalignment, tilt and the decision margins) */
     double slack_y = 2.0 * (g->m_rel * r->Ry + g->m_len) + 1e-3;
     double slack_z = 2.0 * (g->m_rel * r->Rz + g->m_len) + 1e-3;
+    double slack_d = 2.0 * (g->m_rel * r->gdy + g->m_dy) + 1e-4;
     double mz = dxmax * fabs(r->tz);
     double my = fabs(r->tau) * (r->Rz + mz + slack_z) + dxmax * fabs(r->tphi);
     double zlo = r->z - r->Rz - mz - slack_z, zhi = r->z + r->Rz + mz + slack_z;
@@ -493,12 +502,15 @@ static void gather_candidates(const ocfg *g, const otkl *T, const road_t *r, int
     if (glo < 0) glo = 0;
     if (ghi > nrt - 1) ghi = nrt - 1;
     int yb0 = ybin_of(g, ylo), yb1 = ybin_of(g, yhi);
+    int db0 = dbin_of(g, r->dytrk - r->gdy - slack_d), db1 = dbin_of(g, r->dytrk + r->gdy + slack_d);
     for (int gr = (int)glo; gr <= (int)ghi; gr++) {
         int stack = gr / g->n_rows, row = gr % g->n_rows;
         int det = sec * (NSTK * NLAY) + stack * NLAY + l;
-        int64_t base = (((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_yb;
-        uint32_t a = T->offsets[base + yb0], b = T->offsets[base + yb1 + 1];
-        for (uint32_t k = a; k < b; k++) ilist_push(L, T->perm[k]);
+        for (int db = db0; db <= db1; db++) {
+            int64_t base = ((((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_db + db) * g->n_yb;
+            uint32_t a = T->offsets[base + yb0], b = T->offsets[base + yb1 + 1];
+            for (uint32_t k = a; k < b; k++) ilist_push(L, T->perm[k]);
+        }
     }
 }
 

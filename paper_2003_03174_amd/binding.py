@@ -38,15 +38,14 @@ class trd_config(C.Structure):
         ("struct_size", C.c_uint32), ("precision", C.c_int32),
         ("x_layer", C.c_double * 6), ("tilt", C.c_double * 6),
         ("z_min", C.c_double), ("pad_len", C.c_double),
-        ("n_rows", C.c_int32), ("n_yb", C.c_int32),
-        ("y_bin_w", C.c_double), ("drift_len", C.c_double),
+        ("n_rows", C.c_int32), ("n_yb", C.c_int32), ("n_db", C.c_int32), ("flags", C.c_uint32),
+        ("y_bin_w", C.c_double), ("dy_bin_w", C.c_double), ("drift_len", C.c_double),
         ("dx_chamber", C.c_double * 540),
         ("bz", C.c_double), ("x_over_x0", C.c_double), ("mass", C.c_double),
         ("sigma_y", C.c_double * 3), ("sigma_dy", C.c_double * 3), ("tan_psi", C.c_double),
         ("chi2_max", C.c_double), ("n_sigma_dy", C.c_double), ("n_sigma_road", C.c_double),
         ("snp_max", C.c_double),
         ("hbm_budget_bytes", C.c_uint64), ("block_size", C.c_int32), ("search_lanes", C.c_int32),
-        ("flags", C.c_uint32), ("reserved", C.c_uint32),
     ]
 
 
@@ -118,6 +117,7 @@ def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, searc
     c.z_min, c.pad_len = float(params["z_min"]), float(params["pad_len"])
     c.n_rows, c.n_yb = int(params["n_rows"]), int(params["n_yb"])
     c.y_bin_w, c.drift_len = float(params["y_bin_w"]), float(params["drift_len"])
+    c.n_db, c.dy_bin_w = int(params["n_db"]), float(params["dy_bin_w"])
     for d in range(540):
         c.dx_chamber[d] = float(params["dx_chamber"][d])
     c.bz, c.x_over_x0, c.mass = float(params["bz"]), float(params["x_over_x0"]), float(params["mass"])

@@ -18,15 +18,16 @@ struct trd_ctx {
     DevCfg<float> gf{};
     double *d_dx64 = nullptr;
     float *d_dx32 = nullptr;
-    uint32_t *d_small = nullptr;  // [0] fb_count [1] fb_done [2] n_big
+    uint32_t *d_small = nullptr;  // [0] fb_count [1] fb_done
 
     // tracklet-side capacity
     int64_t cap_tkl = 0;
-    uint32_t *d_key = nullptr, *d_rank = nullptr, *d_big = nullptr;
+    uint32_t *d_keys_a = nullptr, *d_keys_b = nullptr;
     float4 *d_sorted = nullptr, *d_tmp = nullptr;
-    // cell-side capacity (entries of count/offsets)
+    uint32_t *d_hist = nullptr, *d_hist_off = nullptr, *d_tiles_tkl = nullptr;
+    // cell-side capacity (entries of offsets minus one)
     int64_t cap_cells = 0;
-    uint32_t *d_count = nullptr, *d_offsets = nullptr, *d_bsums = nullptr;
+    uint32_t *d_offsets = nullptr, *d_tiles_cell = nullptr;
     // track-side capacity
     int64_t cap_trk = 0;
     int32_t *d_fb = nullptr;
@@ -52,9 +53,10 @@ int check_config(const trd_config *c)
     if (!c || c->struct_size != sizeof(trd_config)) return TRD_EINVAL;
     if (c->precision < TRD_PREC_FP64 || c->precision > TRD_PREC_FP32_COV64) return TRD_EINVAL;
     if (c->n_rows < 1 || c->n_rows > 32 || c->n_yb < 1 || c->n_yb > 4096) return TRD_EINVAL;
-    if (!(c->y_bin_w > 0) || !isfinite(c->y_bin_w)) return TRD_EINVAL;
+    if (c->n_db < 1 || c->n_db > 4096) return TRD_EINVAL;
     int ex;
-    if (frexp(c->y_bin_w, &ex) != 0.5) return TRD_EINVAL;  // power of two
+    for (double wb : {c->y_bin_w, c->dy_bin_w})
+        if (!(wb > 0) || !isfinite(wb) || frexp(wb, &ex) != 0.5) return TRD_EINVAL;  // power of two
     if (!finite_all(c->x_layer, 6) || !finite_all(c->tilt, 6) || !finite_all(c->dx_chamber, 540))
         return TRD_EINVAL;
     for (int l = 0; l < 6; l++)
@@ -75,7 +77,7 @@ int check_config(const trd_config *c)
     case 0: case 1: case 4: case 8: case 16: case 32: case 64: break;
     default: return TRD_EINVAL;
     }
-    if (c->reserved != 0) return TRD_EINVAL;
+
     return TRD_OK;
 }
 
@@ -114,8 +116,11 @@ void fill_devcfg(DevCfg<T> &g, const trd_config &c, const T *dx)
     g.dx = dx;
     g.bin.y_min = -c.y_bin_w * c.n_yb / 2.0;
     g.bin.inv_w = 1.0 / c.y_bin_w;
+    g.bin.dy_min = -c.dy_bin_w * c.n_db / 2.0;
+    g.bin.inv_wd = 1.0 / c.dy_bin_w;
     g.bin.n_rows = c.n_rows;
     g.bin.n_yb = c.n_yb;
+    g.bin.n_db = c.n_db;
     g.bin.n_groups = 1;
     g.bin.n_cells = 0;
 }
@@ -143,8 +148,13 @@ template <typename T> void dev_free(T **p)
     *p = nullptr;
 }
 
-int64_t tkl_bytes(int64_t n) { return (int64_t)(n > 0 ? n : 1) * (4 + 4 + 16 + 16) + 4 * (n / 32 + 2); }
-int64_t cell_bytes(int64_t nc) { return 8 * (nc + 1) + 4 * scan_block_sums_len(nc + 1); }
+int64_t hist_len(int64_t n) { return radix_blocks(n > 0 ? n : 1) * 256; }
+int64_t tkl_bytes(int64_t n)
+{
+    const int64_t m = n > 0 ? n : 1;
+    return m * (4 + 4 + 16 + 16) + 8 * hist_len(n) + 4 * scan_block_sums_len(hist_len(n));
+}
+int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1) + 4 * scan_block_sums_len(nc + 1); }
 int64_t trk_bytes(int64_t n) { return 4 * (n > 0 ? n : 1); }
 
 int over_budget(const trd_ctx *ctx, int64_t extra)
@@ -153,32 +163,37 @@ int over_budget(const trd_ctx *ctx, int64_t extra)
     return b != 0 && (uint64_t)(ctx->bytes + extra) > b;
 }
 
+void free_tkl(trd_ctx *ctx)
+{
+    dev_free(&ctx->d_keys_a);
+    dev_free(&ctx->d_keys_b);
+    dev_free(&ctx->d_sorted);
+    dev_free(&ctx->d_tmp);
+    dev_free(&ctx->d_hist);
+    dev_free(&ctx->d_hist_off);
+    dev_free(&ctx->d_tiles_tkl);
+}
+
 int ensure_tkl(trd_ctx *ctx, int64_t n)
 {
-    if (n <= ctx->cap_tkl && ctx->d_key) return TRD_OK;
+    if (n <= ctx->cap_tkl && ctx->d_keys_a) return TRD_OK;
     int64_t cap = n > 2 * ctx->cap_tkl ? n : 2 * ctx->cap_tkl;
-    const int64_t old = ctx->d_key ? tkl_bytes(ctx->cap_tkl) : 0;
+    const int64_t old = ctx->d_keys_a ? tkl_bytes(ctx->cap_tkl) : 0;
     if (over_budget(ctx, tkl_bytes(cap) - old)) {
         cap = n;
         if (over_budget(ctx, tkl_bytes(cap) - old)) return TRD_EBUDGET;
     }
-    dev_free(&ctx->d_key);
-    dev_free(&ctx->d_rank);
-    dev_free(&ctx->d_sorted);
-    dev_free(&ctx->d_tmp);
-    dev_free(&ctx->d_big);
+    free_tkl(ctx);
     ctx->bytes -= old;
     ctx->cap_tkl = 0;
     int64_t acc = 0;
     int rc;
-    if ((rc = dev_alloc(ctx, &ctx->d_key, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_rank, cap, &acc)) ||
+    const int64_t hl = hist_len(cap);
+    if ((rc = dev_alloc(ctx, &ctx->d_keys_a, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_keys_b, cap, &acc)) ||
         (rc = dev_alloc(ctx, &ctx->d_sorted, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_tmp, cap, &acc)) ||
-        (rc = dev_alloc(ctx, &ctx->d_big, cap / 32 + 2, &acc))) {
-        dev_free(&ctx->d_key);
-        dev_free(&ctx->d_rank);
-        dev_free(&ctx->d_sorted);
-        dev_free(&ctx->d_tmp);
-        dev_free(&ctx->d_big);
+        (rc = dev_alloc(ctx, &ctx->d_hist, hl, &acc)) || (rc = dev_alloc(ctx, &ctx->d_hist_off, hl, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_tiles_tkl, scan_block_sums_len(hl), &acc))) {
+        free_tkl(ctx);
         return rc;
     }
     ctx->bytes += tkl_bytes(cap);
@@ -188,22 +203,19 @@ int ensure_tkl(trd_ctx *ctx, int64_t n)
 
 int ensure_cells(trd_ctx *ctx, int64_t nc)
 {
-    if (nc <= ctx->cap_cells && ctx->d_count) return TRD_OK;
-    const int64_t old = ctx->d_count ? cell_bytes(ctx->cap_cells) : 0;
+    if (nc <= ctx->cap_cells && ctx->d_offsets) return TRD_OK;
+    const int64_t old = ctx->d_offsets ? cell_bytes(ctx->cap_cells) : 0;
     if (over_budget(ctx, cell_bytes(nc) - old)) return TRD_EBUDGET;
-    dev_free(&ctx->d_count);
     dev_free(&ctx->d_offsets);
-    dev_free(&ctx->d_bsums);
+    dev_free(&ctx->d_tiles_cell);
     ctx->bytes -= old;
     ctx->cap_cells = 0;
     int64_t acc = 0;
     int rc;
-    if ((rc = dev_alloc(ctx, &ctx->d_count, nc + 1, &acc)) ||
-        (rc = dev_alloc(ctx, &ctx->d_offsets, nc + 1, &acc)) ||
-        (rc = dev_alloc(ctx, &ctx->d_bsums, scan_block_sums_len(nc + 1), &acc))) {
-        dev_free(&ctx->d_count);
+    if ((rc = dev_alloc(ctx, &ctx->d_offsets, nc + 1, &acc)) ||
+        (rc = dev_alloc(ctx, &ctx->d_tiles_cell, scan_block_sums_len(nc + 1), &acc))) {
         dev_free(&ctx->d_offsets);
-        dev_free(&ctx->d_bsums);
+        dev_free(&ctx->d_tiles_cell);
         return rc;
     }
     ctx->bytes += cell_bytes(nc);
@@ -233,7 +245,7 @@ int ensure_trk(trd_ctx *ctx, int64_t n)
 
 int64_t n_cells_of(const trd_config &c, int32_t ng)
 {
-    return (int64_t)ng * TRD_N_DET * c.n_rows * c.n_yb;
+    return (int64_t)ng * TRD_N_DET * c.n_rows * c.n_db * c.n_yb;
 }
 
 int launch_status()
@@ -319,14 +331,17 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
     b.n_cells = (uint32_t)nc;
     ctx->gd.bin = b;
     ctx->gf.bin = b;
-    launch_fill_u32(ctx->d_count, 0u, nc + 1, s);
-    launch_key_hist(t->y, t->z, t->dy, t->det_row, t->group, n, b, ctx->d_key, ctx->d_rank,
-                    ctx->d_count, s);
-    launch_scan(ctx->d_count, nc, ctx->d_bsums, ctx->d_offsets, s);
-    launch_scatter(t->y, t->z, t->dy, ctx->d_key, ctx->d_rank, ctx->d_offsets, n, (uint32_t)nc,
-                   ctx->d_sorted, s);
-    launch_cell_sort(ctx->d_offsets, (uint32_t)nc, ctx->d_sorted, ctx->d_tmp, ctx->d_big,
-                     ctx->d_small + 2, s);
+    BinBuffers buf{};
+    buf.keys_a = ctx->d_keys_a;
+    buf.keys_b = ctx->d_keys_b;
+    buf.sorted = ctx->d_sorted;
+    buf.recs_tmp = ctx->d_tmp;
+    buf.hist = ctx->d_hist;
+    buf.hist_off = ctx->d_hist_off;
+    buf.tiles_tkl = ctx->d_tiles_tkl;
+    buf.offsets = ctx->d_offsets;
+    buf.tiles_cell = ctx->d_tiles_cell;
+    launch_bin(t->y, t->z, t->dy, t->det_row, t->group, n, b, buf, s);
     if ((rc = launch_status())) return rc;
     ctx->loaded = true;
     ctx->n_tkl = n;
@@ -412,14 +427,9 @@ void trd_destroy(trd_ctx *ctx)
     dev_free(&ctx->d_dx64);
     dev_free(&ctx->d_dx32);
     dev_free(&ctx->d_small);
-    dev_free(&ctx->d_key);
-    dev_free(&ctx->d_rank);
-    dev_free(&ctx->d_sorted);
-    dev_free(&ctx->d_tmp);
-    dev_free(&ctx->d_big);
-    dev_free(&ctx->d_count);
+    free_tkl(ctx);
     dev_free(&ctx->d_offsets);
-    dev_free(&ctx->d_bsums);
+    dev_free(&ctx->d_tiles_cell);
     dev_free(&ctx->d_fb);
     delete ctx;
 }

@@ -20,7 +20,9 @@ constexpr uint32_t kStopSnp = 1u, kRotFail = 2u, kOutOfZ = 4u, kFallback = 8u, k
 struct BinCfg {
     double y_min;   // -w * n_yb / 2
     double inv_w;   // 1 / w, exact
-    int32_t n_rows, n_yb, n_groups;
+    double dy_min;  // same for the deflection bins
+    double inv_wd;
+    int32_t n_rows, n_yb, n_db, n_groups;
     uint32_t n_cells;
 };
 
@@ -40,19 +42,25 @@ struct DevCfg {
     BinCfg bin;
 };
 
+// Device buffers of the binning.
+struct BinBuffers {
+    uint32_t *keys_a, *keys_b;  // [cap] cell keys (radix ping-pong)
+    float4 *sorted, *recs_tmp;  // [cap] records (radix ping-pong; result in `sorted`)
+    uint32_t *hist, *hist_off;  // [radix_blocks(cap) * 256] digit histograms
+    uint32_t *tiles_tkl;        // [scan_block_sums_len(radix_blocks(cap) * 256)]
+    uint32_t *offsets;          // [n_cells + 1]
+    uint32_t *tiles_cell;       // [scan_block_sums_len(n_cells + 1)]
+    const uint32_t *sorted_keys;  // set by launch_bin: keys in sorted order
+};
+
 // launchers (stream-ordered, no synchronisation)
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-void launch_key_hist(const float *y, const float *z, const float *dy, const uint32_t *det_row,
-                     const int32_t *grp, int64_t n, const BinCfg &b, uint32_t *key,
-                     uint32_t *rank, uint32_t *count, hipStream_t s);
-void launch_scan(const uint32_t *count, int64_t n, uint32_t *block_sums, uint32_t *offsets,
-                 hipStream_t s);
 int64_t scan_block_sums_len(int64_t n);
-void launch_scatter(const float *y, const float *z, const float *dy, const uint32_t *key,
-                    const uint32_t *rank, const uint32_t *offsets, int64_t n, uint32_t n_cells,
-                    float4 *sorted, hipStream_t s);
-void launch_cell_sort(const uint32_t *offsets, uint32_t n_cells, float4 *sorted, float4 *tmp,
-                      uint32_t *big_list, uint32_t *n_big, hipStream_t s);
+int64_t radix_blocks(int64_t n);
+// sorts the tracklets into cells: buf.sorted in (key, input index) order,
+// buf.offsets[c] = first position of cell c, offsets[n_cells] = valid count
+void launch_bin(const float *y, const float *z, const float *dy, const uint32_t *det_row,
+                const int32_t *grp, int64_t n, const BinCfg &b, BinBuffers &buf, hipStream_t s);
 
 struct MatchIO {
     const float4 *sorted;

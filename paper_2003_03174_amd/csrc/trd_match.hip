@@ -266,12 +266,13 @@ template <typename TS> __device__ __forceinline__ TS poly2(const TS *a, TS s)
     return a[0] + a[1] * s + a[2] * s * s;
 }
 
-// y bin of a window edge, clamped; NaN maps to bin 0 (never out of range)
-__device__ __forceinline__ int ybin(double y, const BinCfg &b)
+// bin of a window edge among n bins starting at lo, clamped; NaN maps to
+// bin 0 (never out of range)
+__device__ __forceinline__ int bin_of(double v, double lo, double inv_w, int n)
 {
-    const double u = floor((y - b.y_min) * b.inv_w);
+    const double u = floor((v - lo) * inv_w);
     if (!(u >= 0.0)) return 0;
-    return u > (double)(b.n_yb - 1) ? b.n_yb - 1 : (int)u;
+    return u > (double)(n - 1) ? n - 1 : (int)u;
 }
 
 // global pad-row index of a z window edge, clamped to [0, nrt - 1]
@@ -293,6 +294,7 @@ struct Road {
     TS y, z, tphi, tz, tau, Ry, Rz, gdy, dytrk, si00, si01, si11;
     int glo, ghi;  // global pad-row range (glo > ghi: nothing to search)
     int yb0, yb1;  // y-bin range
+    int db0, db1;  // deflection-bin range
     int gdet0;     // key-space chamber of stack 0: group * 540 + sector * 30 + layer
     int sdet0;     // misalignment-table chamber of stack 0: sector * 30 + layer
 };
@@ -434,8 +436,11 @@ __device__ __forceinline__ bool open_road(const Trk<TS, TC> &T, int l, int grp, 
     const int nrt = kStacks * g.bin.n_rows;
     R.glo = zrow(T.z - R.Rz - mz - slack_z, g, nrt);
     R.ghi = zrow(T.z + R.Rz + mz + slack_z, g, nrt);
-    R.yb0 = ybin((double)(T.y - R.Ry - my - slack_y), g.bin);
-    R.yb1 = ybin((double)(T.y + R.Ry + my + slack_y), g.bin);
+    R.yb0 = bin_of((double)(T.y - R.Ry - my - slack_y), g.bin.y_min, g.bin.inv_w, g.bin.n_yb);
+    R.yb1 = bin_of((double)(T.y + R.Ry + my + slack_y), g.bin.y_min, g.bin.inv_w, g.bin.n_yb);
+    const TS slack_d = TS(1e-4) + TS(1e-4) * R.gdy;
+    R.db0 = bin_of((double)(R.dytrk - R.gdy - slack_d), g.bin.dy_min, g.bin.inv_wd, g.bin.n_db);
+    R.db1 = bin_of((double)(R.dytrk + R.gdy + slack_d), g.bin.dy_min, g.bin.inv_wd, g.bin.n_db);
     R.sdet0 = T.sec * (kStacks * kLayers) + l;
     R.gdet0 = grp * kDet + R.sdet0;
     return true;
@@ -456,58 +461,51 @@ __device__ __forceinline__ TS cand_chi2(const Road<TS> &R, TS ye, TS ze, const f
 }
 
 // Scan of the road's cells by the G lanes of a group (G = 1: a lone lane).
-// Lane `sub` of the group first fetches the cell range of one pad row, so
-// the ranges of up to G rows arrive in one memory round trip; each range is
-// then broadcast and scanned with kUnroll independent record loads in flight
-// per lane.
+// The road is a set of contiguous record ranges, one per (pad row, dy bin)
+// pair (its y bins are adjacent in the key order); lane `sub` takes every
+// G-th range and walks it with kUnroll record loads in flight.
 template <int G, typename TS>
 __device__ __forceinline__ void scan_road(const Road<TS> &R, int sub, const DevCfg<TS> &g,
                                           const MatchIO &io, Best<TS> &B)
 {
-    constexpr int kUnroll = 4;
+    constexpr int kUnroll = 2;
     const int nr = g.bin.n_rows;
-    const uint32_t nyb = (uint32_t)g.bin.n_yb;
+    const uint32_t nyb = (uint32_t)g.bin.n_yb, ndb = (uint32_t)g.bin.n_db;
+    const int nd = R.db1 - R.db0 + 1;
+    const int nrange = (R.ghi - R.glo + 1) * nd;
     const bool misaligned = g.dx_max != TS(0);
-    for (int c0 = R.glo; c0 <= R.ghi; c0 += G) {
-        uint32_t a_l = 0, b_l = 0;
-        const int gl = c0 + sub;
-        if (gl <= R.ghi) {
-            const int st = gl / nr, rw = gl - st * nr;
-            const uint32_t base = ((uint32_t)(R.gdet0 + st * kLayers) * (uint32_t)nr + (uint32_t)rw) * nyb;
-            a_l = io.offsets[base + R.yb0];
-            b_l = io.offsets[base + R.yb1 + 1];
+    for (int j = sub; j < nrange; j += G) {
+        const int jr = nd == 1 ? j : j / nd;
+        const int gr = R.glo + jr;
+        const int db = R.db0 + (j - jr * nd);
+        const int st = gr / nr, rw = gr - st * nr;
+        const uint32_t base =
+            ((((uint32_t)(R.gdet0 + st * kLayers) * (uint32_t)nr + (uint32_t)rw) * ndb + (uint32_t)db) *
+             nyb);
+        const uint32_t a = io.offsets[base + R.yb0], b = io.offsets[base + R.yb1 + 1];
+        TS ye = R.y, ze = R.z;
+        if (misaligned) {
+            const TS dxd = g.dx[R.sdet0 + st * kLayers];
+            ye = R.y + dxd * R.tphi;
+            ze = R.z + dxd * R.tz;
         }
-        const int nrow = R.ghi - c0 + 1 < G ? R.ghi - c0 + 1 : G;
-        for (int j = 0; j < nrow; j++) {
-            const uint32_t a = G == 1 ? a_l : (uint32_t)__shfl((int)a_l, j, G);
-            const uint32_t b = G == 1 ? b_l : (uint32_t)__shfl((int)b_l, j, G);
-            const int st = (c0 + j) / nr;
-            TS ye = R.y, ze = R.z;
-            if (misaligned) {
-                const TS dxd = g.dx[R.sdet0 + st * kLayers];
-                ye = R.y + dxd * R.tphi;
-                ze = R.z + dxd * R.tz;
-            }
-            for (uint32_t k0 = a + (uint32_t)sub; k0 < b; k0 += G * kUnroll) {
-                float4 rec[kUnroll];
+        for (uint32_t k0 = a; k0 < b; k0 += kUnroll) {
+            float4 rec[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
-                    const uint32_t k = k0 + (uint32_t)(u * G);
-                    if (k < b) rec[u] = io.sorted[k];
-                }
+            for (int u = 0; u < kUnroll; u++)
+                if (k0 + u < b) rec[u] = io.sorted[k0 + u];
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
-                    const uint32_t k = k0 + (uint32_t)(u * G);
-                    if (k < b) {
-                        bool pass;
-                        const TS c = cand_chi2(R, ye, ze, rec[u], g.chi2_max, pass);
-                        const int oj = __float_as_int(rec[u].w);
-                        const bool take = pass && better(c, oj, B);
-                        B.chi2 = take ? c : B.chi2;
-                        B.idx = take ? oj : B.idx;
-                        B.pos = take ? (int)k : B.pos;
-                        B.stack = take ? st : B.stack;
-                    }
+            for (int u = 0; u < kUnroll; u++) {
+                const uint32_t k = k0 + (uint32_t)u;
+                if (k < b) {
+                    bool pass;
+                    const TS c = cand_chi2(R, ye, ze, rec[u], g.chi2_max, pass);
+                    const int oj = __float_as_int(rec[u].w);
+                    const bool take = pass && better(c, oj, B);
+                    B.chi2 = take ? c : B.chi2;
+                    B.idx = take ? oj : B.idx;
+                    B.pos = take ? (int)k : B.pos;
+                    B.stack = take ? st : B.stack;
                 }
             }
         }
@@ -693,17 +691,19 @@ __global__ void __launch_bounds__(256) k_match_coop(DevCfg<float> g, MatchIO io)
     for (int l = 0; l < kLayers; l++) {
         acc.lidx = -1;
         acc.lchi = 0.0f;
-        Road<float> R;
-        R.glo = 1;
-        R.ghi = 0;
         bool search = false;
-        if (live) {
-            if (!predict(T, l, g, status))
-                live = false;
-            else
-                search = open_road(T, l, grp, g, status, R);
+        {
+            Road<float> R;
+            R.glo = 1;
+            R.ghi = 0;
+            if (live) {
+                if (!predict(T, l, g, status))
+                    live = false;
+                else
+                    search = open_road(T, l, grp, g, status, R);
+            }
+            roads[tid] = R;
         }
-        roads[tid] = R;
         wave_sync();
 #pragma unroll 1
         for (int rnd = 0; rnd < G; rnd++) {
@@ -729,7 +729,8 @@ __global__ void __launch_bounds__(256) k_match_coop(DevCfg<float> g, MatchIO io)
         if (search) {
             const Best<float> B = bests[tid];
             if (B.idx != 0x7fffffff) {
-                const int rc = apply_best(T, l, R, B, g, io, status, acc);
+                const Road<float> Rs = roads[tid];  // reloaded: not kept live across the scan
+                const int rc = apply_best(T, l, Rs, B, g, io, status, acc);
                 if (rc == 2 && kFloatCov) {
                     queued = true;
                     live = false;

@@ -50,6 +50,8 @@ def default_params(**over):
         n_rows=N_ROWS,
         n_yb=16,
         y_bin_w=8.0,
+        n_db=1,                                # deflection bins per y bin row
+        dy_bin_w=0.0625,
         drift_len=3.0,
         dx_chamber=np.zeros(N_DET),
         bz=0.5,
@@ -162,7 +164,8 @@ def highland_theta0(p, beta, xi):
 
 def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
                    ineff_frac=0.0, distortion=None, noise_free=False,
-                   ms=True, fp32=True, dtype=np.float64, rho_seed=250.0):
+                   ms=True, fp32=True, dtype=np.float64, rho_seed=250.0, seed_sigma_y=0.1,
+                   seed_sigma_z=0.1):
     """Simulate one group.
 
     pt_dist: "exp" (pT = 0.3 + Exp(1)) or "pow3" (pdf ~ pT^-3 above 0.3).
@@ -171,6 +174,7 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
     distortion: None or (dmin, dmax): random (y, z) displacement of the seed.
     noise_free: seeds are truth, tracklets are exact (z = true z), no MS kicks,
       no rounding to float32.
+    seed_sigma_y, seed_sigma_z: Gaussian errors of the seed's y and z (cm).
     Returns a dict of numpy arrays (see generate()).
     """
     dt = dtype
@@ -206,7 +210,7 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
     seed[4] = qpt
     truth_seed = seed.copy()
 
-    cov0 = np.array([0.1 ** 2, 0.1 ** 2, 1e-3 ** 2, 1e-3 ** 2, 0.01 ** 2])
+    cov0 = np.array([seed_sigma_y ** 2, seed_sigma_z ** 2, 1e-3 ** 2, 1e-3 ** 2, 0.01 ** 2])
     if distortion is not None:
         cov0[0] += (distortion[1] / 3.0) ** 2
         cov0[1] += (distortion[1] / 3.0) ** 2
@@ -215,7 +219,7 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
         cov[j] = cov0[k]
     inp = seed.copy()
     if not noise_free:
-        sig = np.array([0.1, 0.1, 1e-3, 1e-3, 0.01])
+        sig = np.array([seed_sigma_y, seed_sigma_z, 1e-3, 1e-3, 0.01])
         inp += rng.standard_normal((5, n)) * sig[:, None]
         if distortion is not None:
             dd = rng.uniform(distortion[0], distortion[1], n)
@@ -447,9 +451,12 @@ WORKLOADS = {
                           seed=0, params=dict(y_bin_w=8.0, n_yb=16)),
     "c2_frame_20k": dict(n_tracks=20000, pt_dist="exp", fake_ratio=0.5, ineff_frac=0.1,
                          seed=1, params=dict(y_bin_w=8.0, n_yb=16)),
+    # 8 cm y bins x 1/8 cm deflection bins over +-4 cm: the road of a seed
+    # with a 5 cm position error is cut down by the 4 sigma dy window
     "c5_distortion_450k": dict(n_tracks=450000, pt_dist="pow3", fake_ratio=0.5, ineff_frac=0.1,
                                distortion=(5.0, 15.0), seed=4,
-                               params=dict(y_bin_w=2.0, n_yb=64, n_sigma_road=3.0)),
+                               params=dict(y_bin_w=8.0, n_yb=16, dy_bin_w=0.125, n_db=64,
+                                           n_sigma_road=3.0)),
 }
 
 
@@ -515,6 +522,28 @@ def serving_stream(seed=3, n_frames=100, rate_hz=200.0, median=15000, sigma=0.6)
     gaps = rng.exponential(1.0 / rate_hz, n_frames)
     sizes = np.maximum(1, np.round(rng.lognormal(math.log(median), sigma, n_frames))).astype(np.int64)
     return np.cumsum(gaps), sizes
+
+
+DESCRIPTIONS = {
+    "c1_small_fp64": "pT = 0.3 + Exp(1) GeV/c, |eta| < 0.84, 20% uniform fakes, 8 cm y bins",
+    "c2_frame_20k": "pT = 0.3 + Exp(1) GeV/c, 50% uniform fakes, 10% of tracks miss 1-2 layers, "
+                    "8 cm y bins",
+    "c5_distortion_450k": "pT^-3 above 0.3 GeV/c, 50% uniform fakes, 10% inefficiency, 5-15 cm "
+                          "random (y, z) seed displacement, road 3 sigma, 8 cm y x 1/8 cm dy bins",
+    "multiframe_64": "64 frames, U[2000, 40000] tracks each, fakes per true tracklet U[0.2, 0.8], "
+                     "10% inefficiency, group = frame, 8 cm y bins",
+}
+
+
+def describe(name):
+    return DESCRIPTIONS.get(name, name)
+
+
+def load_workload(name):
+    """A named workload: a preset of WORKLOADS or the 64-frame batch."""
+    if name == "multiframe_64":
+        return multiframe_64()
+    return generate(name)
 
 
 def to_device_layout(w):

@@ -27,8 +27,8 @@ def test_library_exports_every_declared_function():
 
 
 def test_config_struct_size_matches_header_layout():
-    # 2 ints + 12 doubles + 2 doubles + 2 ints + 2 doubles + 540 + 3 + 3+3+1 + 4 doubles + u64 + 4 ints
-    assert C.sizeof(B.trd_config) == 8 + 8 * 12 + 16 + 8 + 16 + 8 * 540 + 24 + 56 + 32 + 8 + 16
+    # 2 ints + 12 doubles + 2 doubles + 4 ints + 3 doubles + 540 + 3 + 3+3+1 + 4 doubles + u64 + 2 ints
+    assert C.sizeof(B.trd_config) == 8 + 8 * 12 + 16 + 16 + 24 + 8 * 540 + 24 + 56 + 32 + 8 + 8
 
 
 def test_status_strings():
@@ -47,6 +47,8 @@ def _cfg(**kw):
     lambda c: setattr(c, "struct_size", 12),
     lambda c: setattr(c, "precision", 7),
     lambda c: setattr(c, "y_bin_w", 3.0),          # not a power of two
+    lambda c: setattr(c, "dy_bin_w", 0.1),
+    lambda c: setattr(c, "n_db", 0),
     lambda c: setattr(c, "n_rows", 40),
     lambda c: setattr(c, "snp_max", 1.5),
     lambda c: setattr(c, "pad_len", 7.0),          # rows no longer tile [z_min, -z_min]

@@ -82,6 +82,29 @@ def test_tilted_pads_and_misaligned_chambers(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
+@pytest.mark.parametrize("tilt", [False, True])
+def test_deflection_bins(prec, tilt):
+    """Cells split in dy as well (y bins innermost): binning bit-exact, parity."""
+    params = dict(y_bin_w=8.0, n_yb=16, dy_bin_w=0.125, n_db=64)
+    if tilt:
+        params["tilt"] = synth.tilt_pm2deg()
+        params["dx_chamber"] = np.random.default_rng(9).uniform(-0.5, 0.5, 540)
+    w = workload(None, n_tracks=4000, seed=29, fake_ratio=0.5, ineff_frac=0.1, pt_dist="pow3",
+                 params=params)
+    res = run_gpu(w, prec)
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
+    # Float state with tilted pads: on steep low-pT tracks the slope rounding
+    # reaches y through dx/f^3 (~50 cm per layer) and the tilt term feeds the
+    # y error into tan(lambda) through the gain; measured worst track 1.4e-5,
+    # 99.9 % of tracks within 1e-5.
+    loose = 2e-5 if (tilt and prec != "fp64") else None
+    rep = pu.compare(ref, res, prec, state_tol_max=loose)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
 def test_frame_20k(prec):
     w = workload("c2_frame_20k")
     res = run_gpu(w, prec)

@@ -1,0 +1,50 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case copies the oracle source with one planted mistake (a flipped sign,
+a dropped factor, a transposed operand, a wrong tie rule ...), builds it on
+the CPU and runs the pin suite against it through TRD_ORACLE_LIB; the suite
+must fail.  The real oracle passes the same suite in the other tests.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "trd_oracle.c")
+
+MUTANTS = {
+    "jacobian_dz_dc_sign": ("J[1][4] = k * t * arc * arc", "J[1][4] = -k * t * arc * arc"),
+    "jacobian_dy_ds_f": ("J[0][2] = arc * sinc(delta) / (f1 * f2);", "J[0][2] = arc * sinc(delta) / (f1 * f1);"),
+    "scattering_drops_f2": ("C[2][2] += th2 * f * f * tt;", "C[2][2] += th2 * tt;"),
+    "transport_transposed": ("for (int k = 0; k < 5; k++) a += T[i][k] * J[j][k];",
+                             "for (int k = 0; k < 5; k++) a += T[i][k] * J[k][j];"),
+    "tilt_sign": ("double ry = yj - (ye + r->tau * (ze - zj));", "double ry = yj - (ye - r->tau * (ze - zj));"),
+    "curvature_sign": ("double cu = k * p[4];", "double cu = -k * p[4];"),
+    "rotation_ds_dy_sign": ("J[2][0] = -cu * sa;", "J[2][0] = cu * sa;"),
+    "dy_gate_slope_power": ("C[2][2] / (f3 * f3));", "C[2][2] / (f3));"),
+    "chi2_cross_term": ("2.0 * r->Si[0][1] * ry * rz", "r->Si[0][1] * ry * rz"),
+    "tie_to_higher_index": ("(c2 == bchi && j < best_orig)", "(c2 == bchi && j > best_orig)"),
+    "bin_rounding": ("double u = floor((v - lo) * (1.0 / w));", "double u = floor((v - lo) * (1.0 / w) + 0.5);"),
+    "joseph_drops_kvk": ("for (int a = 0; a < 2; a++)\n                for (int b = 0; b < 2; b++) v += K[i][a] * V[a][b] * K[j][b];", ""),
+    "no_scattering": ("        add_ms(p, C, g);\n\n        /* road", "        /* road"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    src = open(SRC).read()
+    a, b = MUTANTS[name]
+    assert src.count(a) >= 1, f"mutation site of {name} not found"
+    path = tmp_path / f"{name}.c"
+    lib = tmp_path / f"{name}.so"
+    path.write_text(src.replace(a, b, 1))
+    subprocess.run(["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(path), "-lm"], check=True)
+    env = dict(os.environ, TRD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_math.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_search.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"planted mistake {name} passed every pin"

@@ -70,7 +70,7 @@ def test_binned_equals_brute_force(tilt):
     """Identical indices, chi2, states and flags on tiny dense inputs."""
     n_seeds = 60
     for seed in range(n_seeds):
-        params = dict(y_bin_w=4.0, n_yb=32)
+        params = dict(y_bin_w=4.0, n_yb=32, dy_bin_w=0.125, n_db=64 if seed % 2 else 1)
         if tilt:
             params["tilt"] = synth.tilt_pm2deg()
             rng = np.random.default_rng(seed)
@@ -86,8 +86,10 @@ def test_binned_equals_brute_force(tilt):
 def test_independent_of_bin_width_and_order():
     base = _wl(200, 77, fake_ratio=3.0, params=dict(y_bin_w=8.0, n_yb=16))
     ref = O.match(base["params"], base, threads=2)
-    for wb, nyb in ((1.0, 128), (2.0, 64), (4.0, 32), (16.0, 8)):
-        P = synth.default_params(y_bin_w=wb, n_yb=nyb)
+    for wb, nyb, wd, ndb in ((1.0, 128, 0.0625, 1), (2.0, 64, 0.0625, 1), (4.0, 32, 0.0625, 1),
+                             (16.0, 8, 0.0625, 1), (8.0, 16, 0.125, 64), (2.0, 64, 0.0625, 16),
+                             (4.0, 32, 1.0, 8)):
+        P = synth.default_params(y_bin_w=wb, n_yb=nyb, dy_bin_w=wd, n_db=ndb)
         o = O.match(P, base, threads=2)
         assert np.array_equal(o["idx"], ref["idx"])
         assert np.array_equal(o["p"], ref["p"])
@@ -130,6 +132,57 @@ def test_chi2_mean_is_ndf(variant):
     N = c2.size
     assert N > 15000
     assert abs(c2.mean() - 2.0) < 3 * math.sqrt(4.0 / N), c2.mean()
+
+
+def test_chi2_mean_with_correlated_innovation():
+    """Tilted pads, a precise seed y and a 5 cm seed z error: the tilt term
+    ties the y residual to the track's z error (correlation ~0.8), so the
+    chi2 cross term matters; E[chi2] stays 2."""
+    params = dict(chi2_max=1e9, n_sigma_road=12.0, tilt=synth.tilt_pm2deg())
+    w = _wl(2500, 33, fake_ratio=0.0, seed_sigma_z=5.0, params=params)
+    o = O.match(w["params"], w, threads=4)
+    m = (o["idx"][0] >= 0) & (o["idx"][0] == w["true_idx"][0])
+    c2 = o["chi2_layer"][0][m]
+    assert c2.size > 2000
+    assert abs(c2.mean() - 2.0) < 3 * math.sqrt(4.0 / c2.size), c2.mean()
+
+
+@pytest.mark.parametrize("nsig", [1.0, 2.0])
+def test_dy_gate_acceptance(nsig):
+    """The dy exclusion at n sigma keeps a true tracklet with probability
+    2 Phi(n) - 1 when its width is the tracklet error plus the track slope
+    error (all other gates open, no fakes).  First layer only: the dy
+    residual is not used in the update, so a rejection selects tracks whose
+    slope error persists into the next layers."""
+    params = dict(chi2_max=1e9, n_sigma_road=6.0, n_sigma_dy=nsig)
+    w = _wl(4000, 35, fake_ratio=0.0, params=params)
+    o = O.match(w["params"], w, threads=4)
+    avail = w["true_idx"][0] >= 0
+    frac = (o["idx"][0] == w["true_idx"][0])[avail].mean()
+    want = math.erf(nsig / math.sqrt(2.0))
+    n = avail.sum()
+    assert abs(frac - want) < 4 * math.sqrt(want * (1 - want) / n), (frac, want)
+
+
+def test_exact_ties_go_to_the_lower_index():
+    """Duplicated tracklets have identical chi2: the lower input index wins."""
+    w = _wl(300, 37, fake_ratio=0.0)
+    n = w["n_tracklets"]
+    w2 = dict(w)
+    for k in ("tkl_y", "tkl_z", "tkl_dy", "tkl_det_row", "tkl_group"):
+        w2[k] = np.concatenate([w[k], w[k]])       # copies at n..2n-1
+    o1 = O.match(w["params"], w, threads=2)
+    o2 = O.match(w["params"], w2, threads=2)
+    assert np.array_equal(o1["idx"], o2["idx"])
+    assert np.all(o2["idx"] < n)
+    assert (o1["flags"] & O.FL_P3).sum() == 0 and (o2["flags"] & O.FL_P3)[o2["n_match"] > 0].all()
+    # and reversed: originals placed after their copies lose the tie
+    w3 = dict(w)
+    for k in ("tkl_y", "tkl_z", "tkl_dy", "tkl_det_row", "tkl_group"):
+        w3[k] = np.concatenate([w[k][::-1], w[k]])
+    o3 = O.match(w["params"], w3, threads=2)
+    m = o1["idx"] >= 0
+    assert np.array_equal(o3["idx"][m], (n - 1 - o1["idx"])[m])
 
 
 def test_pulls_unit_width():
