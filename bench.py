@@ -39,7 +39,7 @@ def bin_alg_bytes(n_tkl, n_cells):
     return n_tkl * (20 + 20 + 16) + n_cells * 16
 
 
-def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None):
+def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None, flags=0):
     import torch
     from paper_2003_03174_amd import binding as B
     from paper_2003_03174_amd import synth
@@ -47,7 +47,7 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
     if d is None:
         d = B.device_inputs(synth.to_device_layout(w), prec)
     n = w["n_tracks"]
-    m = B.Matcher(w["params"], prec, block_size=block_size, search_lanes=search_lanes)
+    m = B.Matcher(w["params"], prec, block_size=block_size, search_lanes=search_lanes, flags=flags)
     m.reserve(w["n_tracklets"], w["n_groups"], n)
     out = m.alloc_results(n, chi2_layer=False)
     stream = torch.cuda.current_stream()
@@ -141,6 +141,57 @@ def cpu_baseline(w, budget_s=12.0):
                         f"extrapolated to the whole batch"))
 
 
+def serve_bench(args):
+    """Poisson stream of frames served by continuous batching (float path,
+    two slots) against static batching with the plain double kernel."""
+    import numpy as np
+    import torch
+    from paper_2003_03174_amd import serve, synth
+
+    P = synth.default_params()
+    rng = np.random.default_rng(3)
+    n_pool = args.serve_pool
+    sizes = np.maximum(1, np.round(rng.lognormal(math.log(15000), 0.6, n_pool))).astype(int)
+    ss = np.random.SeedSequence(3).spawn(n_pool)
+    log(f"generating {n_pool} frames (lognormal tracks, median 15000)")
+    pool = []
+    for i in range(n_pool):
+        g = synth.generate_group(np.random.default_rng(ss[i]), P, int(sizes[i]), fake_ratio=0.5,
+                                 ineff_frac=0.1)
+        w = synth._concat_groups([g], P)
+        pool.append((w["n_tracks"], w["n_tracklets"], serve.frame_arrays(w)))
+    n_fr = int(args.serve_rate * args.serve_seconds)
+    t = np.cumsum(rng.exponential(1.0 / args.serve_rate, n_fr))
+
+    def stream(times):
+        return [serve.Frame(i, float(times[i]), *pool[i % n_pool][:2], pool[i % n_pool][2])
+                for i in range(len(times))]
+
+    n_of = {i: pool[i % n_pool][0] for i in range(n_fr)}
+    out = {"metric": "served frame latency and tracks/s (continuous batching)", "unit": "ms",
+           "data": "synthetic", "n_gpus": 1,
+           "config": {"workload": f"Poisson {args.serve_rate:g} frames/s for {args.serve_seconds:g} s, "
+                                  f"lognormal tracks (median 15000, sigma 0.6), 50% fakes, "
+                                  f"{n_pool} distinct frames cycled", "hbm_budget_gb": 32}}
+    for name, prec, policy, slots in (("continuous_fp32", "fp32", "continuous", 2),
+                                      ("static_fp64", "fp64", "static", 1)):
+        ex = serve.HipExecutor(P, prec, budget_bytes=32 << 30, n_slots=slots)
+        sched = serve.Scheduler(ex, policy, static_frames=8, static_timeout_s=0.02)
+        sched.run(stream(np.linspace(0, 0.01, 8)))          # warm up
+        torch.cuda.synchronize()
+        log(f"serving {n_fr} frames: {name}")
+        done = sched.run(stream(t))
+        out[name] = serve.summarize(done, n_of)
+        log(f"  {out[name]}")
+        # saturation: every frame present at t = 0
+        sat = sched.run(stream(np.zeros(min(n_fr, 400))))
+        out[name]["saturation_tracks_per_s"] = serve.summarize(sat, n_of)["tracks_per_s"]
+        ex.close()
+    out["value"] = out["continuous_fp32"]["p99_ms"]
+    out["higher_is_better"] = False
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,9 +204,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
     ap.add_argument("--graph", action="store_true", help="replay bin + match as one captured graph")
+    ap.add_argument("--persistent", action="store_true",
+                    help="one-lane-per-track match as a persistent grid")
     ap.add_argument("--autotune", action="store_true", help="pick block size and lanes per track first")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson frame stream)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run a 512 MiB device-to-device copy first (reference for HBM byte counters)")
+                    help="run a 512 MiB elementwise copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the path shards by "
@@ -166,14 +223,18 @@ def main():
     import torch
     from paper_2003_03174_amd import synth
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.serve:
+        serve_bench(args)
+        return
 
     if args.calibrate_copy:
+        # an elementwise kernel that reads 512 MiB and writes 512 MiB once
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        log("calibration copy: 3 x 512 MiB read + 512 MiB written")
+        log("calibration: 3 x (512 MiB read + 512 MiB written) by an elementwise add")
         del src, dst
     log(f"generating {args.workload}")
     w = synth.load_workload(args.workload)
@@ -189,8 +250,9 @@ def main():
         args.block_size, args.search_lanes = tuned["block_size"], tuned["search_lanes"]
         log(f"autotuned: block {args.block_size}, lanes {args.search_lanes} ({tuned['ms']:.3f} ms)")
         del d
+    from paper_2003_03174_amd import binding
     r = run_gpu(w, args.precision, args.steps, args.warmup, args.block_size, args.search_lanes,
-                graph=args.graph)
+                graph=args.graph, flags=binding.TRD_CFG_PERSISTENT if args.persistent else 0)
     ms = r["wall_ms_per_step"]
     match_avg = sum(r["match_ms"]) / len(r["match_ms"])
     bin_avg = sum(r["bin_ms"]) / len(r["bin_ms"])
@@ -216,7 +278,8 @@ def main():
             "graph": bool(args.graph),
             "precision": args.precision,
             "block_size": args.block_size or 256,
-            "search_lanes": args.search_lanes or 8,
+            "search_lanes": args.search_lanes or 1,
+            "persistent": bool(args.persistent),
             "step": "bin all tracklets + match all tracks",
         },
         "latency_ms": {"step_p50": pct(r["step_ms"], 50), "step_p99": pct(r["step_ms"], 99),

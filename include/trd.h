@@ -69,6 +69,10 @@ extern "C" {
 #define TRD_CFG_FAIL_ALLOC 1u     /* test hook: trd_create fails with TRD_ENOMEM */
 #define TRD_CFG_FORCE_FALLBACK 2u /* test hook (TRD_PREC_FP32): every track takes the
                                      double-covariance re-run */
+#define TRD_CFG_PERSISTENT 4u     /* one-lane-per-track matching as a persistent grid
+                                     (resident workgroups pull blocks of tracks from a
+                                     work counter); for large multi-frame batches.
+                                     Requires search_lanes 0 or 1 (else TRD_EINVAL). */
 
 typedef struct trd_ctx trd_ctx;
 
@@ -84,8 +88,8 @@ typedef struct trd_config {
     double z_min;             /* lower z edge of stack 0; chambers span [z_min, -z_min] */
     double pad_len;           /* pad-row length in z */
     int32_t n_rows;           /* pad rows per stack (<= 32) */
-    int32_t n_yb;             /* y bins per (pad row, dy bin) in the tracklet cells */
-    int32_t n_db;             /* deflection (dy) bins per pad row; 1 = no dy binning */
+    int32_t n_yb;             /* y bins per (chamber, dy bin) in the tracklet cells */
+    int32_t n_db;             /* deflection (dy) bins per chamber; 1 = no dy binning */
     uint32_t flags;           /* TRD_CFG_* */
     double y_bin_w;           /* y bin width, a power of two; bins cover
                                  [-n_yb*w/2, n_yb*w/2), outer bins are open */
@@ -106,7 +110,7 @@ typedef struct trd_config {
     int32_t block_size;       /* match workgroup size: 64, 128, 192 or 256; 0 = 256 */
     int32_t search_lanes;     /* float paths: lanes that share one track's road (each
                                  scans whole cell ranges): 1 (one lane per track),
-                                 4, 8, 16, 32 or 64; 0 = 8 */
+                                 4, 8, 16, 32 or 64; 0 = 1 */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */
@@ -161,10 +165,10 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out);
  * Errors: TRD_EINVAL, TRD_ENOMEM, TRD_EBUDGET. */
 int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t max_tracks);
 
-/* Bins the tracklets into (group, chamber, pad row, dy bin, y bin) cells
- * (y bins innermost, so the cells of one (row, dy bin) that overlap a road
- * are contiguous): exact cell keys, counts, exclusive scan and a stable
- * scatter into ctx-owned
+/* Bins the tracklets into (group, chamber, dy bin, y bin, pad row) cells
+ * (pad rows innermost, so the cells of one (dy bin, y bin) that overlap a
+ * road are contiguous): exact cell keys, a stable sort by (cell, input
+ * index) into ctx-owned
  * sorted storage.  The caller may reuse `t`'s buffers once the stream has
  * passed this call.  Tracklets with a det >= 540, a row >= n_rows, a group
  * outside [0, n_groups) or a non-finite value are dropped.

@@ -32,10 +32,10 @@
  *     gate width adds the track slope error: sqrt(s_dy^2 + L^2 C_ss / f^6);
  *   - road half widths n_road * sqrt(S_yy), n_road * sqrt(S_zz) around the
  *     prediction; chi2 <= chi2_max; winner = lexicographic min (chi2, index);
- *   - tracklet cells: key = (((group*540 + det)*n_rows + row)*n_db + dbin)*n_yb
- *     + ybin, ybin = clamp(floor((y - y_min) * (1/w)), 0, n_yb-1) and dbin the
+ *   - tracklet cells: key = (((group*540 + det)*n_db + dbin)*n_yb + ybin)*n_rows
+ *     + row, ybin = clamp(floor((y - y_min) * (1/w)), 0, n_yb-1) and dbin the
  *     same on dy with its own width, both in double; a road is searched over
- *     the pad rows x deflection bins x y bins that overlap it.
+ *     the deflection bins x y bins x pad rows that overlap it.
  *
  * Decision-margin flags mark tracks where a gate, tie or geometric decision
  * lies within a margin, so that a correct implementation in a different
@@ -359,8 +359,8 @@ static int64_t tkl_key(const ocfg *g, double y, double z, double dy, uint32_t de
     if (det >= NDET || (int32_t)row >= g->n_rows || grp < 0 || grp >= n_groups ||
         !isfinite(y) || !isfinite(z) || !isfinite(dy))
         return n_cells_of(g, n_groups);
-    return ((((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_db + dbin_of(g, dy)) * g->n_yb +
-           ybin_of(g, y);
+    return ((((int64_t)grp * NDET + det) * g->n_db + dbin_of(g, dy)) * g->n_yb + ybin_of(g, y)) *
+               g->n_rows + row;
 }
 
 typedef struct { int64_t key; int64_t idx; } keyidx;
@@ -503,14 +503,17 @@ static void gather_candidates(const ocfg *g, const otkl *T, const road_t *r, int
     if (ghi > nrt - 1) ghi = nrt - 1;
     int yb0 = ybin_of(g, ylo), yb1 = ybin_of(g, yhi);
     int db0 = dbin_of(g, r->dytrk - r->gdy - slack_d), db1 = dbin_of(g, r->dytrk + r->gdy + slack_d);
-    for (int gr = (int)glo; gr <= (int)ghi; gr++) {
-        int stack = gr / g->n_rows, row = gr % g->n_rows;
+    for (int stack = (int)glo / g->n_rows; stack <= (int)ghi / g->n_rows; stack++) {
+        int r0 = (int)glo - stack * g->n_rows, r1 = (int)ghi - stack * g->n_rows;
+        if (r0 < 0) r0 = 0;
+        if (r1 > g->n_rows - 1) r1 = g->n_rows - 1;
         int det = sec * (NSTK * NLAY) + stack * NLAY + l;
-        for (int db = db0; db <= db1; db++) {
-            int64_t base = ((((int64_t)grp * NDET + det) * g->n_rows + row) * g->n_db + db) * g->n_yb;
-            uint32_t a = T->offsets[base + yb0], b = T->offsets[base + yb1 + 1];
-            for (uint32_t k = a; k < b; k++) ilist_push(L, T->perm[k]);
-        }
+        for (int db = db0; db <= db1; db++)
+            for (int yb = yb0; yb <= yb1; yb++) {
+                int64_t base = ((((int64_t)grp * NDET + det) * g->n_db + db) * g->n_yb + yb) * g->n_rows;
+                uint32_t a = T->offsets[base + r0], b = T->offsets[base + r1 + 1];
+                for (uint32_t k = a; k < b; k++) ilist_push(L, T->perm[k]);
+            }
     }
 }
 

@@ -21,6 +21,7 @@ PRECISIONS = {"fp64": TRD_PREC_FP64, "fp32": TRD_PREC_FP32, "fp32_cov64": TRD_PR
 TRK_STOP_SNP, TRK_ROT_FAIL, TRK_OUT_OF_Z, TRK_FP64_FALLBACK, TRK_NOT_PD, TRK_BAD_INPUT = 1, 2, 4, 8, 16, 32
 TRD_CFG_FAIL_ALLOC = 1
 TRD_CFG_FORCE_FALLBACK = 2
+TRD_CFG_PERSISTENT = 4
 
 # every symbol include/trd.h declares
 EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_get_binning",

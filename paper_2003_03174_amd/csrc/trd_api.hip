@@ -18,7 +18,8 @@ struct trd_ctx {
     DevCfg<float> gf{};
     double *d_dx64 = nullptr;
     float *d_dx32 = nullptr;
-    uint32_t *d_small = nullptr;  // [0] fb_count [1] fb_done
+    uint32_t *d_small = nullptr;  // [0] fb_count [1] fb_done [2] work_next [3] work_done
+    int n_cu = 0;
 
     // tracklet-side capacity
     int64_t cap_tkl = 0;
@@ -77,7 +78,8 @@ int check_config(const trd_config *c)
     case 0: case 1: case 4: case 8: case 16: case 32: case 64: break;
     default: return TRD_EINVAL;
     }
-
+    // the persistent grid is a one-lane-per-track schedule
+    if ((c->flags & TRD_CFG_PERSISTENT) && c->search_lanes > 1) return TRD_EINVAL;
     return TRD_OK;
 }
 
@@ -293,10 +295,12 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out)
         trd_destroy(ctx);
         return TRD_EDEVICE;
     }
+    if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        ctx->n_cu = 1;
     fill_devcfg(ctx->gd, *cfg, (const double *)ctx->d_dx64);
     fill_devcfg(ctx->gf, *cfg, (const float *)ctx->d_dx32);
     if (ctx->cfg.block_size == 0) ctx->cfg.block_size = 256;
-    if (ctx->cfg.search_lanes == 0) ctx->cfg.search_lanes = 8;
+    if (ctx->cfg.search_lanes == 0) ctx->cfg.search_lanes = 1;
     *out = ctx;
     return TRD_OK;
 }
@@ -384,8 +388,11 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     io.fb_count = ctx->d_small;
     io.fb_done = ctx->d_small + 1;
     io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
+    io.work_next = ctx->d_small + 2;
+    io.work_done = ctx->d_small + 3;
     launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size,
-                 ctx->cfg.search_lanes, (hipStream_t)hip_stream);
+                 ctx->cfg.search_lanes, (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu,
+                 (hipStream_t)hip_stream);
     return launch_status();
 }
 

@@ -1,14 +1,15 @@
 // Tracklet binning for gfx950.
 //
-// Every tracklet gets an exact cell key (group, chamber, pad row, dy bin, y
-// bin); the tracklets are then ordered by (key, input index) with a stable
+// Every tracklet gets an exact cell key (group, chamber, dy bin, y bin, pad
+// row); the tracklets are then ordered by (key, input index) with a stable
 // least-significant-digit radix sort over 8-bit digits that carries the
 // 16-byte search record (y, dy, z, input index) along.  Digit histograms
 // live in LDS, ranks come from wavefront ballots, so there are no global
 // atomics.  Cell offsets follow from the run boundaries of the sorted keys
 // and a suffix minimum.  The search road of a track is then a few contiguous
-// record ranges, one per (pad row, dy bin): the covariance road of Sect. 3
-// of the paper, enumerated through the cells it overlaps.
+// record ranges, one per (stack, dy bin, y bin) holding all its pad rows: the
+// covariance road of Sect. 3 of the paper, enumerated through the cells it
+// overlaps.
 #include "trd_internal.h"
 
 namespace trd {
@@ -43,8 +44,38 @@ __device__ __forceinline__ uint32_t cell_key(float y, float z, float dy, uint32_
     const int yb = !(u >= 0.0) ? 0 : (u > (double)(b.n_yb - 1) ? b.n_yb - 1 : (int)u);
     const double v = floor(((double)dy - b.dy_min) * b.inv_wd);
     const int db = !(v >= 0.0) ? 0 : (v > (double)(b.n_db - 1) ? b.n_db - 1 : (int)v);
-    return ((((uint32_t)grp * kDet + det) * (uint32_t)b.n_rows + row) * (uint32_t)b.n_db +
-            (uint32_t)db) * (uint32_t)b.n_yb + (uint32_t)yb;
+    return ((((uint32_t)grp * kDet + det) * (uint32_t)b.n_db + (uint32_t)db) * (uint32_t)b.n_yb +
+            (uint32_t)yb) * (uint32_t)b.n_rows + row;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of v over the workgroup; *total receives the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; w++) {
+        off += (w < wid) ? wsum[w] : 0u;
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
 }
 
 // Source of the radix passes: the caller's tracklet arrays on the first
@@ -96,15 +127,25 @@ __global__ void __launch_bounds__(kBlock)
 // Stable scatter of one tile: elements are taken in input order (sub-tile,
 // wavefront, lane); a lane's rank among equal digits of its wavefront comes
 // from eight ballots, the counts of earlier wavefronts and sub-tiles from LDS.
+// The tile is first regrouped by digit in LDS, so that each digit's run goes
+// out as contiguous stores.
 __global__ void __launch_bounds__(kBlock)
-    k_radix_scatter(RadixSrc src, BinCfg b, int64_t n, int shift,
+    k_radix_scatter(RadixSrc src, BinCfg b, int64_t n, int shift, const uint32_t *__restrict__ hist,
                     const uint32_t *__restrict__ hist_off, uint32_t *__restrict__ keys_out,
                     float4 *__restrict__ recs_out)
 {
-    __shared__ uint32_t run[kBins];
+    __shared__ uint32_t run[kBins];      // elements of each digit placed so far in this tile
+    __shared__ uint32_t loc[kBins];      // first LDS slot of each digit in this tile
+    __shared__ uint32_t glob[kBins];     // first global position of each digit for this tile
     __shared__ uint32_t wcnt[kBlock / 64][kBins];
+    __shared__ uint32_t skey[kSortTile];
+    __shared__ float4 srec[kSortTile];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    run[tid] = hist_off[(int64_t)tid * gridDim.x + blockIdx.x];
+    const uint32_t cnt = hist[(int64_t)tid * gridDim.x + blockIdx.x];
+    uint32_t tot;
+    loc[tid] = block_excl_scan(cnt, &tot);
+    glob[tid] = hist_off[(int64_t)tid * gridDim.x + blockIdx.x];
+    run[tid] = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; w++) wcnt[w][tid] = 0;
     __syncthreads();
@@ -127,20 +168,29 @@ __global__ void __launch_bounds__(kBlock)
         if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int w = 0; w < wv; w++) pos += wcnt[w][d];
-            keys_out[pos] = key;
-            recs_out[pos] = rec;
+            uint32_t r = run[d] + rank;
+            for (int w = 0; w < wv; w++) r += wcnt[w][d];
+            skey[loc[d] + r] = key;
+            srec[loc[d] + r] = rec;
         }
         __syncthreads();
-        uint32_t tot = 0;
+        uint32_t t = 0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; w++) {
-            tot += wcnt[w][tid];
+            t += wcnt[w][tid];
             wcnt[w][tid] = 0;
         }
-        run[tid] += tot;
+        run[tid] += t;
         __syncthreads();
+    }
+    // slot p holds the (p - loc[d])-th element of digit d in this tile
+    const int nv = (int)tot;
+    for (int p = tid; p < nv; p += kBlock) {
+        const uint32_t key = skey[p];
+        const uint32_t d = (key >> shift) & (kBins - 1);
+        const uint32_t pos = glob[d] + (uint32_t)p - loc[d];
+        keys_out[pos] = key;
+        recs_out[pos] = srec[p];
     }
 }
 
@@ -152,36 +202,6 @@ __global__ void __launch_bounds__(kBlock)
     if (p >= n) return;
     const uint32_t k = keys[p];
     if (p == 0 || keys[p - 1] != k) offsets[k] = (uint32_t)p;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
-
-// Exclusive scan of v over the workgroup; *total receives the sum.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
-{
-    __shared__ uint32_t wsum[kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint32_t incl = wave_incl_scan(v);
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; w++) {
-        off += (w < wid) ? wsum[w] : 0u;
-        tot += wsum[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return off + incl - v;
 }
 
 // load the kScanItems values owned by this thread (pad past the end)
@@ -201,6 +221,22 @@ __device__ __forceinline__ void load_items(const uint32_t *in, int64_t n, int64_
     } else {
 #pragma unroll
         for (int j = 0; j < kScanItems; j++) v[j] = (base + j < n) ? in[base + j] : pad;
+    }
+}
+
+// store the kScanItems values owned by this thread (nothing past the end)
+__device__ __forceinline__ void store_items(uint32_t *out, int64_t n, int64_t base,
+                                            const uint32_t (&v)[kScanItems])
+{
+    if (base + kScanItems <= n) {
+        uint4 *q = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+        for (int j = 0; j < kScanItems / 4; j++)
+            q[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; j++)
+            if (base + j < n) out[base + j] = v[j];
     }
 }
 
@@ -244,12 +280,13 @@ __global__ void __launch_bounds__(kBlock)
     for (int j = 0; j < kScanItems; j++) s += v[j];
     uint32_t tot;
     uint32_t run = block_excl_scan(s, &tot) + tile_off[blockIdx.x];
+    uint32_t o[kScanItems];
 #pragma unroll
-    for (int j = 0; j < kScanItems; j++)
-        if (base + j < n) {
-            out[base + j] = run;
-            run += v[j];
-        }
+    for (int j = 0; j < kScanItems; j++) {
+        o[j] = run;
+        run += v[j];
+    }
+    store_items(out, n, base, o);
 }
 
 // ---- suffix minimum (offsets of empty cells = start of the next run) ----
@@ -341,8 +378,9 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int j = kScanItems - 1; j >= 0; j--) {
         run = v[j] < run ? v[j] : run;
-        if (base + j < n) a[base + j] = run;
+        v[j] = run;
     }
+    store_items(a, n, base, v);
 }
 
 inline unsigned grid_for(int64_t n, int block)
@@ -408,7 +446,7 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
                                buf.hist);
             launch_excl_scan(buf.hist, nblk * kBins, buf.tiles_tkl, buf.hist_off, s);
             hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, b, n, shift,
-                               buf.hist_off, kdst[out], rdst[out]);
+                               buf.hist, buf.hist_off, kdst[out], rdst[out]);
             src.keys = kdst[out];
             src.recs = rdst[out];
             out ^= 1;

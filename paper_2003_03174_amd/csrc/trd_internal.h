@@ -78,11 +78,14 @@ struct MatchIO {
     uint32_t *fb_count;  // [1]
     uint32_t *fb_done;   // [1]
     int force_fallback;  // test hook: queue every track for the re-run
+    uint32_t *work_next; // [1] persistent launch: next block of tracks
+    uint32_t *work_done; // [1] persistent launch: finished workgroups
 };
 
 // precision: 0 = FP64, 1 = FP32 (+ fallback), 2 = FP32 state / FP64 covariance
 // lanes: lanes that scan one track's road together (1 = one lane per track)
+// persistent: one resident grid pulling blocks of tracks (lanes == 1 only)
 void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
-                  const MatchIO &io, int block, int lanes, hipStream_t s);
+                  const MatchIO &io, int block, int lanes, bool persistent, int n_cu, hipStream_t s);
 
 }  // namespace trd

@@ -304,8 +304,8 @@ template <typename TS>
 struct Best {
     TS chi2;
     int idx;    // input-order tracklet index, INT_MAX if none
-    int pos;    // sorted position of the record
     int stack;  // stack of its chamber
+    float y, z; // its measurement
 };
 
 template <typename TS> __device__ __forceinline__ Best<TS> no_best()
@@ -313,8 +313,9 @@ template <typename TS> __device__ __forceinline__ Best<TS> no_best()
     Best<TS> b;
     b.chi2 = TS(INFINITY);
     b.idx = 0x7fffffff;
-    b.pos = 0;
     b.stack = 0;
+    b.y = 0.f;
+    b.z = 0.f;
     return b;
 }
 
@@ -460,55 +461,121 @@ __device__ __forceinline__ TS cand_chi2(const Road<TS> &R, TS ye, TS ze, const f
     return chi2;
 }
 
-// Scan of the road's cells by the G lanes of a group (G = 1: a lone lane).
-// The road is a set of contiguous record ranges, one per (pad row, dy bin)
-// pair (its y bins are adjacent in the key order); lane `sub` takes every
-// G-th range and walks it with kUnroll record loads in flight.
-template <int G, typename TS>
-__device__ __forceinline__ void scan_road(const Road<TS> &R, int sub, const DevCfg<TS> &g,
-                                          const MatchIO &io, Best<TS> &B)
+// The road as record ranges: one per (stack, dy bin, y bin), each holding the
+// road's pad rows of that stack (rows are innermost in the cell key).
+struct RangeGrid {
+    int s0, nd, ny, n;  // first stack, dy bins, y bins, number of ranges
+};
+
+template <typename TS>
+__device__ __forceinline__ RangeGrid range_grid(const Road<TS> &R, int nr)
+{
+    RangeGrid q;
+    q.s0 = R.glo / nr;
+    q.nd = R.db1 - R.db0 + 1;
+    q.ny = R.yb1 - R.yb0 + 1;
+    q.n = (R.glo <= R.ghi) ? (R.ghi / nr - q.s0 + 1) * q.nd * q.ny : 0;
+    return q;
+}
+
+// cell-offset bounds of range (is, id, iy): [*a, *b)
+template <typename TS>
+__device__ __forceinline__ void range_bounds(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                             int st, int id, int iy, uint32_t *a, uint32_t *b)
+{
+    const int nr = g.bin.n_rows;
+    int r0 = R.glo - st * nr, r1 = R.ghi - st * nr;
+    r0 = r0 < 0 ? 0 : r0;
+    r1 = r1 > nr - 1 ? nr - 1 : r1;
+    const uint32_t base = ((((uint32_t)(R.gdet0 + st * kLayers)) * (uint32_t)g.bin.n_db +
+                           (uint32_t)(R.db0 + id)) * (uint32_t)g.bin.n_yb + (uint32_t)(R.yb0 + iy)) *
+                          (uint32_t)nr;
+    *a = io.offsets[base + r0];
+    *b = io.offsets[base + r1 + 1];
+}
+
+// Gate and keep the best of the records [a, b) of one stack's chamber.
+template <typename TS>
+__device__ __forceinline__ void scan_range(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                           uint32_t a, uint32_t b, int st, Best<TS> &B)
 {
     constexpr int kUnroll = 2;
-    const int nr = g.bin.n_rows;
-    const uint32_t nyb = (uint32_t)g.bin.n_yb, ndb = (uint32_t)g.bin.n_db;
-    const int nd = R.db1 - R.db0 + 1;
-    const int nrange = (R.ghi - R.glo + 1) * nd;
-    const bool misaligned = g.dx_max != TS(0);
-    for (int j = sub; j < nrange; j += G) {
-        const int jr = nd == 1 ? j : j / nd;
-        const int gr = R.glo + jr;
-        const int db = R.db0 + (j - jr * nd);
-        const int st = gr / nr, rw = gr - st * nr;
-        const uint32_t base =
-            ((((uint32_t)(R.gdet0 + st * kLayers) * (uint32_t)nr + (uint32_t)rw) * ndb + (uint32_t)db) *
-             nyb);
-        const uint32_t a = io.offsets[base + R.yb0], b = io.offsets[base + R.yb1 + 1];
-        TS ye = R.y, ze = R.z;
-        if (misaligned) {
-            const TS dxd = g.dx[R.sdet0 + st * kLayers];
-            ye = R.y + dxd * R.tphi;
-            ze = R.z + dxd * R.tz;
+    TS ye = R.y, ze = R.z;
+    if (g.dx_max != TS(0)) {
+        const TS dxd = g.dx[R.sdet0 + st * kLayers];
+        ye = R.y + dxd * R.tphi;
+        ze = R.z + dxd * R.tz;
+    }
+    for (uint32_t k0 = a; k0 < b; k0 += kUnroll) {
+        float4 rec[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++)
+            if (k0 + u < b) rec[u] = io.sorted[k0 + u];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint32_t k = k0 + (uint32_t)u;
+            if (k < b) {
+                bool pass;
+                const TS c = cand_chi2(R, ye, ze, rec[u], g.chi2_max, pass);
+                const int oj = __float_as_int(rec[u].w);
+                const bool take = pass && better(c, oj, B);
+                B.chi2 = take ? c : B.chi2;
+                B.idx = take ? oj : B.idx;
+                B.stack = take ? st : B.stack;
+                B.y = take ? rec[u].x : B.y;
+                B.z = take ? rec[u].z : B.z;
+            }
         }
-        for (uint32_t k0 = a; k0 < b; k0 += kUnroll) {
-            float4 rec[kUnroll];
+    }
+}
+
+// One lane walks a whole road: the bounds of up to kBatch ranges are fetched
+// in one memory round trip, then their records are gated.
+template <typename TS>
+__device__ __forceinline__ void scan_road_lane(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                               Best<TS> &B)
+{
+    constexpr int kBatch = 4;
+    const RangeGrid q = range_grid(R, g.bin.n_rows);
+    int is = 0, id = 0, iy = 0;
+    for (int j0 = 0; j0 < q.n; j0 += kBatch) {
+        uint32_t a[kBatch], b[kBatch];
+        int st[kBatch];
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++)
-                if (k0 + u < b) rec[u] = io.sorted[k0 + u];
-#pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
-                const uint32_t k = k0 + (uint32_t)u;
-                if (k < b) {
-                    bool pass;
-                    const TS c = cand_chi2(R, ye, ze, rec[u], g.chi2_max, pass);
-                    const int oj = __float_as_int(rec[u].w);
-                    const bool take = pass && better(c, oj, B);
-                    B.chi2 = take ? c : B.chi2;
-                    B.idx = take ? oj : B.idx;
-                    B.pos = take ? (int)k : B.pos;
-                    B.stack = take ? st : B.stack;
+        for (int u = 0; u < kBatch; u++) {
+            a[u] = 0;
+            b[u] = 0;
+            st[u] = q.s0 + is;
+            if (j0 + u < q.n) {
+                range_bounds(R, g, io, st[u], id, iy, &a[u], &b[u]);
+                if (++iy == q.ny) {
+                    iy = 0;
+                    if (++id == q.nd) {
+                        id = 0;
+                        ++is;
+                    }
                 }
             }
         }
+#pragma unroll
+        for (int u = 0; u < kBatch; u++)
+            if (a[u] < b[u]) scan_range(R, g, io, a[u], b[u], st[u], B);
+    }
+}
+
+// G lanes share a road: lane `sub` takes every G-th range.
+template <int G, typename TS>
+__device__ __forceinline__ void scan_road_group(const Road<TS> &R, int sub, const DevCfg<TS> &g,
+                                                const MatchIO &io, Best<TS> &B)
+{
+    const RangeGrid q = range_grid(R, g.bin.n_rows);
+    const int per_stack = q.nd * q.ny;
+    for (int j = sub; j < q.n; j += G) {
+        const int is = j / per_stack, rem = j - is * per_stack;
+        const int id = rem / q.ny, iy = rem - id * q.ny;
+        uint32_t a, b;
+        range_bounds(R, g, io, q.s0 + is, id, iy, &a, &b);
+        scan_range(R, g, io, a, b, q.s0 + is, B);
     }
 }
 
@@ -530,8 +597,7 @@ __device__ __forceinline__ int apply_best(Trk<TS, TC> &T, int l, const Road<TS> 
                                           const DevCfg<TS> &g, const MatchIO &io, uint32_t &status,
                                           Acc<TS> &acc)
 {
-    const float4 r = io.sorted[B.pos];
-    const TS yj = TS(r.x), zj = TS(r.z);
+    const TS yj = TS(B.y), zj = TS(B.z);
     const TS bdx = g.dx[R.sdet0 + B.stack * kLayers];
     if (bdx != TS(0)) {
         if (!propagate(T, g.x_layer[l] + bdx, g)) {
@@ -617,7 +683,7 @@ __device__ __forceinline__ bool match_lane(const DevCfg<TS> &g, const MatchIO &i
         if (live && !predict(T, l, g, status)) live = false;
         if (live && open_road(T, l, grp, g, status, R)) {
             Best<TS> B = no_best<TS>();
-            scan_road<1>(R, 0, g, io, B);
+            scan_road_lane(R, g, io, B);
             if (B.idx != 0x7fffffff) {
                 const int rc = apply_best(T, l, R, B, g, io, status, acc);
                 if (rc == 2 && kQueueNotPD) return false;
@@ -638,6 +704,34 @@ __global__ void __launch_bounds__(256) k_match(DevCfg<TS> g, MatchIO io)
     if (i >= io.n) return;
     if (!match_lane<TS, TC, kFloatCov>(g, io, i, 0u))
         io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
+}
+
+// Persistent variant: a grid sized to the resident capacity of the device
+// pulls blocks of tracks from a work counter until every block is taken
+// (each workgroup exits once the counter passes the last block).  The last
+// workgroup to finish clears the counter for the next launch.
+template <typename TS, typename TC, bool kFloatCov>
+__global__ void __launch_bounds__(256) k_match_persistent(DevCfg<TS> g, MatchIO io)
+{
+    __shared__ uint32_t blk;
+    const uint32_t nblk = (uint32_t)((io.n + blockDim.x - 1) / blockDim.x);
+    for (;;) {
+        if (threadIdx.x == 0) blk = atomicAdd(io.work_next, 1u);
+        __syncthreads();
+        const uint32_t b = blk;
+        __syncthreads();
+        if (b >= nblk) break;
+        const int64_t i = (int64_t)b * blockDim.x + threadIdx.x;
+        if (i < io.n && !match_lane<TS, TC, kFloatCov>(g, io, i, 0u))
+            io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(io.work_done, 1u) == gridDim.x - 1) {
+            atomicExch(io.work_next, 0u);
+            atomicExch(io.work_done, 0u);
+        }
+    }
 }
 
 // Re-run of the queued tracks with a double covariance.  The last
@@ -710,18 +804,20 @@ __global__ void __launch_bounds__(256) k_match_coop(DevCfg<float> g, MatchIO io)
             const int slot = wbase + rnd * (64 / G) + gid;
             const Road<float> Q = roads[slot];
             Best<float> B = no_best<float>();
-            if (Q.glo <= Q.ghi) scan_road<G>(Q, sub, g, io, B);
+            if (Q.glo <= Q.ghi) scan_road_group<G>(Q, sub, g, io, B);
 #pragma unroll
             for (int off = G / 2; off >= 1; off >>= 1) {
                 const float oc = __shfl_xor(B.chi2, off, 64);
                 const int oi = __shfl_xor(B.idx, off, 64);
-                const int op = __shfl_xor(B.pos, off, 64);
                 const int os = __shfl_xor(B.stack, off, 64);
+                const float oy = __shfl_xor(B.y, off, 64);
+                const float oz = __shfl_xor(B.z, off, 64);
                 const bool take = better(oc, oi, B);
                 B.chi2 = take ? oc : B.chi2;
                 B.idx = take ? oi : B.idx;
-                B.pos = take ? op : B.pos;
                 B.stack = take ? os : B.stack;
+                B.y = take ? oy : B.y;
+                B.z = take ? oz : B.z;
             }
             if (sub == 0) bests[slot] = B;
         }
@@ -764,21 +860,44 @@ void launch_coop(int lanes, const DevCfg<float> &gf, const MatchIO &io, unsigned
 
 }  // namespace
 
+template <typename TS, typename TC, bool kFloatCov>
+unsigned persistent_grid(int block, int n_cu, unsigned grid)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_match_persistent<TS, TC, kFloatCov>,
+                                                     block, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const unsigned cap = (unsigned)(per_cu * (n_cu > 0 ? n_cu : 1));
+    return grid < cap ? grid : cap;
+}
+
+template <typename TS, typename TC, bool kFloatCov>
+void launch_lane(const DevCfg<TS> &g, const MatchIO &io, unsigned grid, int block, bool persistent,
+                 int n_cu, hipStream_t s)
+{
+    if (persistent) {
+        const unsigned pg = persistent_grid<TS, TC, kFloatCov>(block, n_cu, grid);
+        hipLaunchKernelGGL((k_match_persistent<TS, TC, kFloatCov>), dim3(pg), dim3(block), 0, s, g, io);
+    } else {
+        hipLaunchKernelGGL((k_match<TS, TC, kFloatCov>), dim3(grid), dim3(block), 0, s, g, io);
+    }
+}
+
 void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
-                  const MatchIO &io, int block, int lanes, hipStream_t s)
+                  const MatchIO &io, int block, int lanes, bool persistent, int n_cu, hipStream_t s)
 {
     if (io.n <= 0) return;
     const unsigned grid = (unsigned)((io.n + block - 1) / block);
     if (precision == 0) {
-        hipLaunchKernelGGL((k_match<double, double, false>), dim3(grid), dim3(block), 0, s, gd, io);
+        launch_lane<double, double, false>(gd, io, grid, block, persistent, n_cu, s);
     } else if (precision == 2) {
         if (lanes == 1)
-            hipLaunchKernelGGL((k_match<float, double, false>), dim3(grid), dim3(block), 0, s, gf, io);
+            launch_lane<float, double, false>(gf, io, grid, block, persistent, n_cu, s);
         else
             launch_coop<double, false>(lanes, gf, io, grid, block, s);
     } else {
         if (lanes == 1)
-            hipLaunchKernelGGL((k_match<float, float, true>), dim3(grid), dim3(block), 0, s, gf, io);
+            launch_lane<float, float, true>(gf, io, grid, block, persistent, n_cu, s);
         else
             launch_coop<float, true>(lanes, gf, io, grid, block, s);
         hipLaunchKernelGGL(k_match_fallback, dim3(64), dim3(256), 0, s, gf, io);

@@ -182,8 +182,9 @@ BYTES_PER_CELL = 4 + 1
 
 class HipExecutor:
     """n_slots streams, each with a matcher context and flat device / pinned
-    host buffers sized from the HBM budget (slot capacity = budget / n_slots);
-    every batch uses contiguous views of exactly its size."""
+    host buffers sized from the HBM budget (slot capacity = budget / n_slots,
+    at most max_batch_tracks tracks); every batch uses contiguous views of
+    exactly its size."""
 
     IN_TRK = {"p": 5, "cov": 15, "x": 1, "sector": 1, "group": 1}
     IN_TKL = {"y": 1, "z": 1, "dy": 1, "det_row": 1, "tgroup": 1}
@@ -191,7 +192,8 @@ class HipExecutor:
            "n_match": 1, "status": 1}
 
     def __init__(self, params, precision="fp32", budget_bytes=32 << 30, n_slots=2,
-                 tracklets_per_track=12.0, max_groups=256, device=0, block_size=0, search_lanes=0):
+                 tracklets_per_track=12.0, max_groups=256, device=0, block_size=0, search_lanes=0,
+                 max_batch_tracks=2_000_000):
         import torch
 
         from . import binding as B
@@ -205,7 +207,7 @@ class HipExecutor:
         if per_slot <= 0:
             raise ValueError("HBM budget too small for the cell tables of one slot")
         per_track = BYTES_PER_TRACK + tracklets_per_track * BYTES_PER_TRACKLET
-        self.cap_tracks = int(per_slot // per_track)
+        self.cap_tracks = int(min(per_slot // per_track, max_batch_tracks))
         self.cap_tracklets = int(self.cap_tracks * tracklets_per_track)
         dev = torch.device("cuda", device)
         f = torch.float64 if precision == "fp64" else torch.float32

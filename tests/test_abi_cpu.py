@@ -55,6 +55,7 @@ def _cfg(**kw):
     lambda c: setattr(c, "block_size", 100),
     lambda c: setattr(c, "block_size", 512),
     lambda c: setattr(c, "search_lanes", 3),
+    lambda c: (setattr(c, "search_lanes", 8), setattr(c, "flags", B.TRD_CFG_PERSISTENT)),
     lambda c: c.x_layer.__setitem__(2, float("nan")),
 ])
 def test_create_rejects_bad_config(mutate):

@@ -36,13 +36,13 @@ def _capture(m, d, n_groups, out):
     return g
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_graph_replays_equal_eager(prec):
+@pytest.mark.parametrize("prec,flags", [("fp32", 0), ("fp64", 0), ("fp32", B.TRD_CFG_PERSISTENT)])
+def test_graph_replays_equal_eager(prec, flags):
     w = synth.generate_frames(5, 8, [1500, 300, 2500, 1, 900, 2000, 1200, 700],
                               [0.5] * 8, params_over=dict(y_bin_w=8.0, n_yb=16), ineff_frac=0.1)
     d = B.device_inputs(synth.to_device_layout(w), prec)
     n = w["n_tracks"]
-    m = B.Matcher(w["params"], prec)
+    m = B.Matcher(w["params"], prec, flags=flags)
     m.reserve(w["n_tracklets"], w["n_groups"], n)
     out = m.alloc_results(n)
     m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])

@@ -28,11 +28,11 @@ def workload(name, **kw):
     return _cache[key]
 
 
-def run_gpu(w, prec, block_size=0, params=None, search_lanes=0):
+def run_gpu(w, prec, block_size=0, params=None, search_lanes=0, flags=0):
     P = params or w["params"]
     lay = synth.to_device_layout(w)
     d = B.device_inputs(lay, prec)
-    m = B.Matcher(P, prec, block_size=block_size, search_lanes=search_lanes)
+    m = B.Matcher(P, prec, block_size=block_size, search_lanes=search_lanes, flags=flags)
     m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
     out = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
     torch.cuda.synchronize()
@@ -264,3 +264,23 @@ def test_launch_shapes_agree(prec):
         o = run_gpu(w, prec, block_size=bs, search_lanes=lanes)
         for k in ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status"):
             assert np.array_equal(o[k], base[k], equal_nan=True), (bs, lanes, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
+def test_persistent_grid_agrees(prec):
+    """The persistent grid (resident workgroups pulling blocks of tracks) runs
+    the same per-track arithmetic: bit-identical to the plain launch, also on
+    a second call through the same context (work counter cleared)."""
+    w = workload("c2_frame_20k")
+    base = run_gpu(w, prec, block_size=256, search_lanes=1)
+    P = w["params"]
+    d = B.device_inputs(synth.to_device_layout(w), prec)
+    for bs in (64, 256):
+        m = B.Matcher(P, prec, block_size=bs, search_lanes=1, flags=B.TRD_CFG_PERSISTENT)
+        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+        for call in range(2):
+            o = pu.to_numpy(m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"]))
+            torch.cuda.synchronize()
+            for k in ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status"):
+                assert np.array_equal(o[k], base[k], equal_nan=True), (bs, call, k)
+        m.close()

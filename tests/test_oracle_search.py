@@ -42,9 +42,9 @@ def test_bin_key_geometry():
     ymin = -wb * nyb / 2
     for i in range(0, w["n_tracklets"], 7):
         k = O.key(P, w["tkl_y"][i], w["tkl_z"][i], w["tkl_dy"][i], int(w["tkl_det_row"][i]))
-        yb = k % nyb
-        row = (k // nyb) % 18
-        det = k // (nyb * 18)
+        row = k % 18
+        yb = (k // 18) % nyb
+        det = k // (nyb * 18 * P["n_db"])
         assert det == w["tkl_det"][i] and row == w["tkl_row"][i]
         y = w["tkl_y"][i]
         lo, hi = ymin + yb * wb, ymin + (yb + 1) * wb
