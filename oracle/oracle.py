@@ -35,6 +35,7 @@ class OCfg(C.Structure):
         ("m_rel", C.c_double), ("m_len", C.c_double), ("m_dy", C.c_double),
         ("m_chi2", C.c_double), ("m_snp", C.c_double),
         ("n_rows", C.c_int32), ("n_yb", C.c_int32), ("n_db", C.c_int32),
+        ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
     ]
 
 
@@ -102,6 +103,8 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
     c.n_sigma_road, c.snp_max = P["n_sigma_road"], P["snp_max"]
     c.m_rel, c.m_len, c.m_dy, c.m_chi2, c.m_snp = margin_rel, m_len, m_dy, m_chi2, m_snp
     c.n_rows, c.n_yb = P["n_rows"], P["n_yb"]
+    c.n_hyp = int(P.get("n_hyp", 0))
+    c.chi2_penalty = float(P.get("chi2_penalty", P["chi2_max"]))
     return c
 
 

@@ -78,6 +78,8 @@ typedef struct {
     double chi2_max, n_sigma_dy, n_sigma_road, snp_max;
     double m_rel, m_len, m_dy, m_chi2, m_snp; /* decision margins */
     int32_t n_rows, n_yb, n_db;
+    int32_t n_hyp;              /* 0: single best candidate; >= 1: hypotheses kept per layer */
+    double chi2_penalty;        /* cost of a layer without a tracklet (hypothesis mode) */
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -691,6 +693,248 @@ done:
     if (o->n_cand) o->n_cand[i] = ncand;
 }
 
+/* ---------------------------------------------------------------------- */
+/* several hypotheses per track (Sect. 3 and Fig. 2: the best N_candidates */
+/* hypotheses of a layer are the seeds of the next one)                    */
+/* ---------------------------------------------------------------------- */
+
+/* Readings where the paper is silent:
+ *   - a hypothesis is one path through the layers; its cost is the sum of
+ *     the chi2 of its tracklets plus chi2_penalty for every layer where it
+ *     takes none;
+ *   - every hypothesis has, at every layer, one child per candidate passing
+ *     all gates of its own road and one child without a tracklet (also when
+ *     it is outside the chambers or has stopped: it then only carries its
+ *     cost forward);
+ *   - the children of all hypotheses are ordered by (cost, with-tracklet
+ *     before without, parent rank, tracklet index) and the first n_hyp
+ *     survive; a child with a tracklet is then propagated precisely to it and
+ *     updated exactly as in the single-hypothesis matcher;
+ *   - the answer is the first hypothesis after the last layer.
+ * With n_hyp = 1 and chi2_penalty >= chi2_max this is the single best
+ * candidate rule. */
+
+#define MAX_HYP 16
+
+typedef struct {
+    double p[5], C[5][5], x;
+    int sec, live, nmatch;
+    unsigned status;
+    double cost, chi2sum;
+    int32_t idx[NLAY];
+    double chi2l[NLAY];
+} hyp_t;
+
+typedef struct {
+    double cost, chi2;
+    int parent;   /* rank of the parent hypothesis */
+    int64_t j;    /* tracklet, -1: none at this layer */
+} child_t;
+
+typedef struct { child_t *v; int64_t n, cap; } clist;
+
+static void clist_push(clist *L, double cost, double chi2, int parent, int64_t j)
+{
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 64;
+        L->v = (child_t *)realloc(L->v, sizeof(child_t) * (size_t)L->cap);
+    }
+    child_t c = {cost, chi2, parent, j};
+    L->v[L->n++] = c;
+}
+
+static int cmp_child(const void *a, const void *b)
+{
+    const child_t *u = (const child_t *)a, *v = (const child_t *)b;
+    if (u->cost != v->cost) return u->cost < v->cost ? -1 : 1;
+    int nu = u->j < 0, nv = v->j < 0;
+    if (nu != nv) return nu - nv;
+    if (u->parent != v->parent) return u->parent < v->parent ? -1 : 1;
+    if (u->j != v->j) return u->j < v->j ? -1 : 1;
+    return 0;
+}
+
+/* Propagation to layer l, sector hops and the layer's scattering. */
+static int hyp_predict(const ocfg *g, hyp_t *h, int l, unsigned *lf)
+{
+    const double tan10 = tan(M_PI / NSEC), dphi = 2.0 * M_PI / NSEC;
+    double xl = g->x_layer[l];
+    if (!propagate(h->p, h->C, &h->x, xl, g, lf, NULL)) {
+        h->status |= ST_STOP_SNP;
+        return 0;
+    }
+    for (int nrot = 0;; nrot++) {
+        double ylim = xl * tan10;
+        if (near_lim(fabs(h->p[0]), ylim, g->m_rel, g->m_len)) *lf |= FL_P4;
+        if (fabs(h->p[0]) <= ylim) break;
+        if (nrot == 2) { h->status |= ST_ROT_FAIL; return 0; }
+        int up = h->p[0] > 0;
+        if (!rotate(h->p, h->C, &h->x, up ? dphi : -dphi, g, NULL)) { h->status |= ST_ROT_FAIL; return 0; }
+        h->sec = (h->sec + (up ? 1 : NSEC - 1)) % NSEC;
+        if (!propagate(h->p, h->C, &h->x, xl, g, lf, NULL)) { h->status |= ST_STOP_SNP; return 0; }
+    }
+    add_ms(h->p, h->C, g);
+    return 1;
+}
+
+/* Road of a predicted hypothesis (same quantities as the single matcher). */
+static void hyp_road(const ocfg *g, const hyp_t *h, int l, road_t *r)
+{
+    r->y = h->p[0]; r->z = h->p[1]; r->s = h->p[2]; r->t = h->p[3];
+    r->f = sqrt(1.0 - r->s * r->s);
+    r->tphi = r->s / r->f;
+    r->tz = r->t / r->f;
+    r->tau = g->tilt[l];
+    double sy = poly2(g->sigma_y, r->s);
+    double vz = g->pad_len * g->pad_len / 12.0;
+    double Syy = h->C[0][0] + 2.0 * r->tau * h->C[0][1] + r->tau * r->tau * h->C[1][1] + sy * sy;
+    double Syz = h->C[0][1] + r->tau * h->C[1][1];
+    double Szz = h->C[1][1] + vz;
+    double det = Syy * Szz - Syz * Syz;
+    r->Si[0][0] = Szz / det;
+    r->Si[1][1] = Syy / det;
+    r->Si[0][1] = r->Si[1][0] = -Syz / det;
+    r->Ry = g->n_sigma_road * sqrt(Syy);
+    r->Rz = g->n_sigma_road * sqrt(Szz);
+    r->dytrk = g->drift_len * (r->tphi - g->tan_psi);
+    double sdy = poly2(g->sigma_dy, r->s);
+    double f3 = r->f * r->f * r->f;
+    r->gdy = g->n_sigma_dy * sqrt(sdy * sdy + g->drift_len * g->drift_len * h->C[2][2] / (f3 * f3));
+}
+
+/* A candidate near the edge of the kept set: its cost, and whether a gate
+ * decision on it lies within the margins. */
+typedef struct { double cost; int passed; } edge_t;
+
+static void match_one_beam(const ocfg *g, int64_t i, int64_t n, const double *ip, const double *ic,
+                           const double *ix, const int32_t *isec, const int32_t *igrp, const otkl *T,
+                           double dxmax, const oout *o, ilist *L, clist *K, clist *E)
+{
+    const int N = g->n_hyp < MAX_HYP ? g->n_hyp : MAX_HYP;
+    hyp_t H[MAX_HYP], Hn[MAX_HYP];
+    int nh = 1;
+    unsigned flags = 0;
+    int64_t ncand = 0;
+    const double vz = g->pad_len * g->pad_len / 12.0;
+    hyp_t *h0 = &H[0];
+    memset(h0, 0, sizeof(*h0));
+    double pk[15];
+    for (int k = 0; k < 5; k++) h0->p[k] = ip[k * n + i];
+    for (int k = 0; k < 15; k++) pk[k] = ic[k * n + i];
+    unpack(pk, h0->C);
+    h0->x = ix[i];
+    h0->sec = isec[i];
+    int grp = igrp ? igrp[i] : 0;
+    for (int l = 0; l < NLAY; l++) { h0->idx[l] = -1; h0->chi2l[l] = 0.0; }
+    int bad = !(isfinite(h0->x) && h0->sec >= 0 && h0->sec < NSEC && grp >= 0 && grp < T->n_groups);
+    for (int k = 0; k < 5; k++) bad |= !isfinite(h0->p[k]);
+    for (int k = 0; k < 15; k++) bad |= !isfinite(pk[k]);
+    if (!bad) bad = !(fabs(h0->p[2]) < g->snp_max) || !ldl_pd(h0->C);
+    if (bad) {
+        h0->status = ST_BAD_INPUT;
+        goto done;
+    }
+    h0->live = 1;
+
+    for (int l = 0; l < NLAY; l++) {
+        K->n = 0;
+        E->n = 0;
+        for (int h = 0; h < nh; h++) {
+            hyp_t *Hh = &H[h];
+            if (Hh->live) Hh->live = hyp_predict(g, Hh, l, &flags);
+            if (Hh->live) {
+                road_t r;
+                hyp_road(g, Hh, l, &r);
+                double mz = dxmax * fabs(r.tz);
+                double wlo = r.z - r.Rz - mz, whi = r.z + r.Rz + mz, zmax = -g->z_min;
+                if (near_lim(whi, g->z_min, g->m_rel, g->m_len) || near_lim(wlo, zmax, g->m_rel, g->m_len))
+                    flags |= FL_P4;
+                if (whi < g->z_min || wlo > zmax) {
+                    Hh->status |= ST_OUT_OF_Z;
+                } else {
+                    gather_candidates(g, T, &r, grp, Hh->sec, l, dxmax, L);
+                    ncand += L->n;
+                    for (int64_t a = 0; a < L->n; a++) {
+                        int64_t j = L->v[a];
+                        double c2;
+                        unsigned fail, nm;
+                        eval_cand(g, &r, T->y[j], T->z[j], T->dy[j], g->dx_chamber[T->det_row[j] >> 5],
+                                  &c2, &fail, &nm);
+                        if (!fail) clist_push(K, Hh->cost + c2, c2, h, j);
+                        /* a gate decision within the margins: passing near a
+                         * limit, or failing exactly one gate by a margin */
+                        if ((!fail && nm) || (fail && popcount4(fail) == 1 && (fail & nm)))
+                            clist_push(E, Hh->cost + c2, c2, h, fail ? 1 : 0);
+                    }
+                }
+            }
+            clist_push(K, Hh->cost + g->chi2_penalty, 0.0, h, -1);
+        }
+        qsort(K->v, (size_t)K->n, sizeof(child_t), cmp_child);
+        int nk = K->n < N ? (int)K->n : N;
+        /* decisions within the margins: the edge of the kept set, the final
+         * winner, and gate decisions on children that would be kept */
+        double edge = K->v[nk - 1].cost;
+        if (K->n > nk && K->v[nk].cost - edge <= g->m_rel * fabs(edge) + g->m_chi2) flags |= FL_P3;
+        if (l == NLAY - 1 && nk > 1 && K->v[1].cost - K->v[0].cost <= g->m_rel * fabs(K->v[0].cost) + g->m_chi2)
+            flags |= FL_P3;
+        for (int64_t a = 0; a < E->n; a++)
+            if (E->v[a].cost <= edge + g->m_rel * fabs(edge) + g->m_chi2)
+                flags |= E->v[a].j ? FL_P2 : FL_P1;
+        for (int k = 0; k < nk; k++) {
+            const child_t *c = &K->v[k];
+            hyp_t *d = &Hn[k];
+            *d = H[c->parent];
+            d->cost = c->cost;
+            if (c->j < 0 || !d->live) continue;
+            int64_t j = c->j;
+            double dxj = g->dx_chamber[T->det_row[j] >> 5];
+            if (dxj != 0.0 && !propagate(d->p, d->C, &d->x, g->x_layer[l] + dxj, g, &flags, NULL)) {
+                d->status |= ST_STOP_SNP;
+                d->live = 0;
+                continue;
+            }
+            double ry = T->y[j] - (d->p[0] + g->tilt[l] * (d->p[1] - T->z[j]));
+            double rz = T->z[j] - d->p[1];
+            double syu = poly2(g->sigma_y, d->p[2]);
+            kalman_update(d->p, d->C, ry, rz, g->tilt[l], syu * syu, vz);
+            d->idx[l] = (int32_t)j;
+            d->chi2l[l] = c->chi2;
+            d->nmatch++;
+            d->chi2sum += c->chi2;
+            if (near_lim(fabs(d->p[2]), g->snp_max, g->m_rel, g->m_snp)) flags |= FL_P4;
+            if (!(fabs(d->p[2]) < g->snp_max)) {
+                d->status |= ST_STOP_SNP;
+                d->live = 0;
+            }
+        }
+        memcpy(H, Hn, sizeof(hyp_t) * (size_t)nk);
+        nh = nk;
+    }
+done:
+    {
+        hyp_t *b = &H[0];
+        pack(b->C, pk);
+        for (int k = 0; k < 5; k++) o->p[k * n + i] = b->p[k];
+        for (int k = 0; k < 15; k++) o->c[k * n + i] = pk[k];
+        for (int l = 0; l < NLAY; l++) {
+            o->idx[l * n + i] = b->idx[l];
+            if (o->chi2_layer) o->chi2_layer[l * n + i] = b->chi2l[l];
+            if (o->lx) o->lx[l * n + i] = NAN;
+            if (o->lsec) o->lsec[l * n + i] = -1;
+        }
+        o->x[i] = b->x;
+        o->sec[i] = b->sec;
+        o->chi2[i] = b->chi2sum;
+        o->n_match[i] = b->nmatch;
+        o->status[i] = b->status;
+        o->flags[i] = flags;
+        /* the answer depends on every layer's selection */
+        if (o->flag_layer) o->flag_layer[i] = flags ? 0 : NLAY;
+        if (o->n_cand) o->n_cand[i] = ncand;
+    }
+}
+
 /* Matches every track.  mode 0: binned search over the sorted cells;
  * mode 1: brute force over all tracklets of the same group/sector/layer. */
 int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *tc,
@@ -726,10 +970,17 @@ int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *t
 #pragma omp parallel
     {
         ilist L = {NULL, 0, 0};
+        clist K = {NULL, 0, 0}, E = {NULL, 0, 0};
 #pragma omp for schedule(dynamic, 256)
-        for (int64_t i = 0; i < n_trk; i++)
-            match_one(g, i, n_trk, tp, tc, tx, tsec, tgrp, &T, dxmax, &o, &L);
+        for (int64_t i = 0; i < n_trk; i++) {
+            if (g->n_hyp >= 1)
+                match_one_beam(g, i, n_trk, tp, tc, tx, tsec, tgrp, &T, dxmax, &o, &L, &K, &E);
+            else
+                match_one(g, i, n_trk, tp, tc, tx, tsec, tgrp, &T, dxmax, &o, &L);
+        }
         free(L.v);
+        free(K.v);
+        free(E.v);
     }
     free(perm);
     free(offsets);

@@ -563,6 +563,84 @@ __device__ __forceinline__ void scan_road_lane(const Road<TS> &R, const DevCfg<T
     }
 }
 
+// Gate one record of stack st and keep it if it beats the best so far.
+template <typename TS>
+__device__ __forceinline__ void gate_record(const Road<TS> &R, const DevCfg<TS> &g, const float4 &rec,
+                                            int st, TS dxd, Best<TS> &B)
+{
+    const TS ye = R.y + dxd * R.tphi, ze = R.z + dxd * R.tz;
+    bool pass;
+    const TS c = cand_chi2(R, ye, ze, rec, g.chi2_max, pass);
+    const int oj = __float_as_int(rec.w);
+    const bool take = pass && better(c, oj, B);
+    B.chi2 = take ? c : B.chi2;
+    B.idx = take ? oj : B.idx;
+    B.stack = take ? st : B.stack;
+    B.y = take ? rec.x : B.y;
+    B.z = take ? rec.z : B.z;
+}
+
+// One lane walks a whole road with its records flattened: the bounds of up
+// to kBatch ranges come in one memory round trip, then their records are
+// taken kU at a time across range boundaries, so a round trip fetches kU
+// records however the road's candidates fall into cells.
+template <typename TS>
+__device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                               Best<TS> &B)
+{
+    constexpr int kBatch = 4, kU = 4;
+    const RangeGrid q = range_grid(R, g.bin.n_rows);
+    const bool shifted = g.dx_max != TS(0);
+    int is = 0, id = 0, iy = 0;
+    for (int j0 = 0; j0 < q.n; j0 += kBatch) {
+        uint32_t a[kBatch], e[kBatch];
+        int st[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+            a[u] = 0;
+            e[u] = 0;
+            st[u] = q.s0 + is;
+            if (j0 + u < q.n) {
+                range_bounds(R, g, io, st[u], id, iy, &a[u], &e[u]);
+                if (++iy == q.ny) {
+                    iy = 0;
+                    if (++id == q.nd) {
+                        id = 0;
+                        ++is;
+                    }
+                }
+            }
+        }
+        // running record counts at the range starts
+        const uint32_t p1 = (e[0] > a[0] ? e[0] - a[0] : 0u);
+        const uint32_t p2 = p1 + (e[1] > a[1] ? e[1] - a[1] : 0u);
+        const uint32_t p3 = p2 + (e[2] > a[2] ? e[2] - a[2] : 0u);
+        const uint32_t tot = p3 + (e[3] > a[3] ? e[3] - a[3] : 0u);
+        for (uint32_t f0 = 0; f0 < tot; f0 += kU) {
+            float4 rec[kU];
+            int su[kU];
+            TS dxd[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                const uint32_t f = f0 + (uint32_t)u;
+                const uint32_t k = f < p1 ? a[0] + f
+                                 : f < p2 ? a[1] + (f - p1)
+                                 : f < p3 ? a[2] + (f - p2)
+                                          : a[3] + (f - p3);
+                su[u] = f < p1 ? st[0] : f < p2 ? st[1] : f < p3 ? st[2] : st[3];
+                dxd[u] = TS(0);
+                if (f < tot) {
+                    rec[u] = io.sorted[k];
+                    if (shifted) dxd[u] = g.dx[R.sdet0 + su[u] * kLayers];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; u++)
+                if (f0 + (uint32_t)u < tot) gate_record(R, g, rec[u], su[u], dxd[u], B);
+        }
+    }
+}
+
 // G lanes share a road: lane `sub` takes every G-th range.
 template <int G, typename TS>
 __device__ __forceinline__ void scan_road_group(const Road<TS> &R, int sub, const DevCfg<TS> &g,
@@ -683,7 +761,7 @@ __device__ __forceinline__ bool match_lane(const DevCfg<TS> &g, const MatchIO &i
         if (live && !predict(T, l, g, status)) live = false;
         if (live && open_road(T, l, grp, g, status, R)) {
             Best<TS> B = no_best<TS>();
-            scan_road_lane(R, g, io, B);
+            scan_road_flat(R, g, io, B);
             if (B.idx != 0x7fffffff) {
                 const int rc = apply_best(T, l, R, B, g, io, status, acc);
                 if (rc == 2 && kQueueNotPD) return false;

@@ -29,6 +29,9 @@ MUTANTS = {
     "bin_rounding": ("double u = floor((v - lo) * (1.0 / w));", "double u = floor((v - lo) * (1.0 / w) + 0.5);"),
     "joseph_drops_kvk": ("for (int a = 0; a < 2; a++)\n                for (int b = 0; b < 2; b++) v += K[i][a] * V[a][b] * K[j][b];", ""),
     "no_scattering": ("        add_ms(p, C, g);\n\n        /* road", "        /* road"),
+    "beam_first_parent_state": ("*d = H[c->parent];", "*d = H[0];"),
+    "beam_cost_not_carried": ("d->cost = c->cost;", ""),
+    "beam_sum_holds_cost": ("d->chi2sum += c->chi2;", "d->chi2sum += c->cost;"),
 }
 
 
@@ -45,6 +48,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, TRD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_math.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_search.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_search.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_beam.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} passed every pin"
