@@ -111,6 +111,15 @@ typedef struct trd_config {
     int32_t search_lanes;     /* float paths: lanes that share one track's road (each
                                  scans whole cell ranges): 1 (one lane per track),
                                  4, 8, 16, 32 or 64; 0 = 1 */
+    int32_t n_hyp;            /* hypotheses kept per layer (Sect. 3, Fig. 2: the best
+                                 N_candidates hypotheses of a layer seed the next):
+                                 0 = the single best candidate per layer; 1, 2, 4 or 8 =
+                                 that many paths, each costing the chi2 of its tracklets
+                                 plus chi2_penalty per layer without one; the answer is
+                                 the cheapest path after the last layer.  Requires
+                                 search_lanes 0 or 1 and no TRD_CFG_PERSISTENT. */
+    double chi2_penalty;      /* cost of a layer without a tracklet (n_hyp >= 1);
+                                 >= chi2_max makes n_hyp = 1 the single best rule */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */

@@ -47,6 +47,7 @@ class trd_config(C.Structure):
         ("chi2_max", C.c_double), ("n_sigma_dy", C.c_double), ("n_sigma_road", C.c_double),
         ("snp_max", C.c_double),
         ("hbm_budget_bytes", C.c_uint64), ("block_size", C.c_int32), ("search_lanes", C.c_int32),
+        ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
     ]
 
 
@@ -132,6 +133,8 @@ def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, searc
     c.block_size = int(block_size)
     c.search_lanes = int(search_lanes)
     c.flags = int(flags)
+    c.n_hyp = int(params.get("n_hyp", 0))
+    c.chi2_penalty = float(params.get("chi2_penalty", params["chi2_max"]))
     return c
 
 

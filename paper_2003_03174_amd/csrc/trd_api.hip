@@ -80,6 +80,12 @@ int check_config(const trd_config *c)
     }
     // the persistent grid is a one-lane-per-track schedule
     if ((c->flags & TRD_CFG_PERSISTENT) && c->search_lanes > 1) return TRD_EINVAL;
+    switch (c->n_hyp) {
+    case 0: case 1: case 2: case 4: case 8: break;
+    default: return TRD_EINVAL;
+    }
+    if (c->n_hyp > 0 && (c->search_lanes > 1 || (c->flags & TRD_CFG_PERSISTENT))) return TRD_EINVAL;
+    if (c->n_hyp > 0 && !(c->chi2_penalty >= 0 && c->chi2_penalty < 1e30)) return TRD_EINVAL;
     return TRD_OK;
 }
 
@@ -108,6 +114,7 @@ void fill_devcfg(DevCfg<T> &g, const trd_config &c, const T *dx)
     g.n_sigma_dy = (T)c.n_sigma_dy;
     g.n_sigma_road = (T)c.n_sigma_road;
     g.snp_max = (T)c.snp_max;
+    g.chi2_penalty = (T)c.chi2_penalty;
     const double dphi = 2.0 * M_PI / TRD_N_SECTORS;
     g.tan_half_sector = (T)tan(0.5 * dphi);
     g.cos_sector = (T)cos(dphi);
@@ -390,9 +397,12 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
     io.work_next = ctx->d_small + 2;
     io.work_done = ctx->d_small + 3;
-    launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size,
-                 ctx->cfg.search_lanes, (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu,
-                 (hipStream_t)hip_stream);
+    if (ctx->cfg.n_hyp > 0)
+        launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, (hipStream_t)hip_stream);
+    else
+        launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size,
+                     ctx->cfg.search_lanes, (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu,
+                     (hipStream_t)hip_stream);
     return launch_status();
 }
 

@@ -36,6 +36,7 @@ struct DevCfg {
     T x_over_x0, mass2;
     T sigma_y[3], sigma_dy[3], tan_psi;
     T chi2_max, n_sigma_dy, n_sigma_road, snp_max;
+    T chi2_penalty;                            // cost of a layer without a tracklet (hypotheses)
     T tan_half_sector, cos_sector, sin_sector;  // tan(10 deg), cos/sin(20 deg)
     T dx_max;
     const T *dx;                               // [540] device
@@ -84,6 +85,9 @@ struct MatchIO {
 
 // precision: 0 = FP64, 1 = FP32 (+ fallback), 2 = FP32 state / FP64 covariance
 // lanes: lanes that scan one track's road together (1 = one lane per track)
+// several hypotheses per track: n_hyp lanes per track (1, 2, 4 or 8)
+void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf, const MatchIO &io,
+                 int n_hyp, hipStream_t s);
 // persistent: one resident grid pulling blocks of tracks (lanes == 1 only)
 void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
                   const MatchIO &io, int block, int lanes, bool persistent, int n_cu, hipStream_t s);

@@ -306,6 +306,17 @@ struct Best {
     int idx;    // input-order tracklet index, INT_MAX if none
     int stack;  // stack of its chamber
     float y, z; // its measurement
+
+    // keeps a passing candidate if it is the lexicographic (chi2, index) minimum
+    __device__ __forceinline__ void offer(TS c, int oj, float yy, float zz, int st, bool pass)
+    {
+        const bool take = pass && (c < chi2 || (c == chi2 && oj < idx));
+        chi2 = take ? c : chi2;
+        idx = take ? oj : idx;
+        stack = take ? st : stack;
+        y = take ? yy : y;
+        z = take ? zz : z;
+    }
 };
 
 template <typename TS> __device__ __forceinline__ Best<TS> no_best()
@@ -563,30 +574,24 @@ __device__ __forceinline__ void scan_road_lane(const Road<TS> &R, const DevCfg<T
     }
 }
 
-// Gate one record of stack st and keep it if it beats the best so far.
-template <typename TS>
+// Gate one record of stack st and offer it to the accumulator.
+template <typename TS, typename A>
 __device__ __forceinline__ void gate_record(const Road<TS> &R, const DevCfg<TS> &g, const float4 &rec,
-                                            int st, TS dxd, Best<TS> &B)
+                                            int st, TS dxd, A &acc)
 {
     const TS ye = R.y + dxd * R.tphi, ze = R.z + dxd * R.tz;
     bool pass;
     const TS c = cand_chi2(R, ye, ze, rec, g.chi2_max, pass);
-    const int oj = __float_as_int(rec.w);
-    const bool take = pass && better(c, oj, B);
-    B.chi2 = take ? c : B.chi2;
-    B.idx = take ? oj : B.idx;
-    B.stack = take ? st : B.stack;
-    B.y = take ? rec.x : B.y;
-    B.z = take ? rec.z : B.z;
+    acc.offer(c, __float_as_int(rec.w), rec.x, rec.z, st, pass);
 }
 
 // One lane walks a whole road with its records flattened: the bounds of up
 // to kBatch ranges come in one memory round trip, then their records are
 // taken kU at a time across range boundaries, so a round trip fetches kU
 // records however the road's candidates fall into cells.
-template <typename TS>
+template <typename TS, typename A>
 __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
-                                               Best<TS> &B)
+                                               A &B)
 {
     constexpr int kBatch = 4, kU = 4;
     const RangeGrid q = range_grid(R, g.bin.n_rows);
@@ -936,7 +941,332 @@ void launch_coop(int lanes, const DevCfg<float> &gf, const MatchIO &io, unsigned
     }
 }
 
+// ---- several hypotheses per track ------------------------------------------
+// A group of N lanes (aligned inside the wavefront) holds one track; lane h
+// holds the hypothesis of rank h.  Per layer every lane predicts its own
+// hypothesis and keeps the N cheapest of its children in registers; N rounds
+// of a group-wide minimum over the children's keys (cost, with-tracklet
+// first, parent rank, tracklet index) then pick the survivors, and lane r
+// takes the state of the r-th survivor's parent by cross-lane reads.
+
+// the N cheapest passing candidates of one hypothesis, ascending (cost, index)
+template <typename TS, int N>
+struct TopN {
+    TS base;  // the hypothesis' cost so far
+    TS cost[N], chi2[N];
+    int idx[N], stack[N];
+    float y[N], z[N];
+
+    __device__ __forceinline__ void init(TS b)
+    {
+        base = b;
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            cost[k] = TS(INFINITY);
+            chi2[k] = TS(0);
+            idx[k] = 0x7fffffff;
+            stack[k] = 0;
+            y[k] = 0.f;
+            z[k] = 0.f;
+        }
+    }
+
+    __device__ __forceinline__ void offer(TS c, int oj, float yy, float zz, int st, bool pass)
+    {
+        const TS cc = base + c;
+        if (!pass) return;
+        // before[k]: the new entry sorts before entry k (monotone in k)
+        bool before[N];
+#pragma unroll
+        for (int k = 0; k < N; k++) before[k] = cc < cost[k] || (cc == cost[k] && oj < idx[k]);
+#pragma unroll
+        for (int k = N - 1; k >= 1; k--) {
+            const bool sh = before[k - 1], put = before[k] && !before[k - 1];
+            cost[k] = sh ? cost[k - 1] : (put ? cc : cost[k]);
+            chi2[k] = sh ? chi2[k - 1] : (put ? c : chi2[k]);
+            idx[k] = sh ? idx[k - 1] : (put ? oj : idx[k]);
+            stack[k] = sh ? stack[k - 1] : (put ? st : stack[k]);
+            y[k] = sh ? y[k - 1] : (put ? yy : y[k]);
+            z[k] = sh ? z[k - 1] : (put ? zz : z[k]);
+        }
+        cost[0] = before[0] ? cc : cost[0];
+        chi2[0] = before[0] ? c : chi2[0];
+        idx[0] = before[0] ? oj : idx[0];
+        stack[0] = before[0] ? st : stack[0];
+        y[0] = before[0] ? yy : y[0];
+        z[0] = before[0] ? zz : z[0];
+    }
+
+    __device__ __forceinline__ void pop()
+    {
+#pragma unroll
+        for (int k = 0; k < N - 1; k++) {
+            cost[k] = cost[k + 1];
+            chi2[k] = chi2[k + 1];
+            idx[k] = idx[k + 1];
+            stack[k] = stack[k + 1];
+            y[k] = y[k + 1];
+            z[k] = z[k + 1];
+        }
+        cost[N - 1] = TS(INFINITY);
+        idx[N - 1] = 0x7fffffff;
+    }
+};
+
+template <typename TS, typename TC>
+struct Hyp {
+    Trk<TS, TC> T;
+    TS cost, chi2sum;
+    int nmatch, live, valid;
+    uint32_t status;
+    int idx[kLayers];
+    TS chi2l[kLayers];
+};
+
+// lane src's hypothesis (every lane of the group takes part)
+template <typename TS, typename TC>
+__device__ __forceinline__ void pull(Hyp<TS, TC> &H, int src)
+{
+    H.T.y = __shfl(H.T.y, src, 64);
+    H.T.z = __shfl(H.T.z, src, 64);
+    H.T.s = __shfl(H.T.s, src, 64);
+    H.T.t = __shfl(H.T.t, src, 64);
+    H.T.c = __shfl(H.T.c, src, 64);
+    H.T.x = __shfl(H.T.x, src, 64);
+#pragma unroll
+    for (int k = 0; k < 15; k++) H.T.C[k] = __shfl(H.T.C[k], src, 64);
+    H.T.sec = __shfl(H.T.sec, src, 64);
+    H.cost = __shfl(H.cost, src, 64);
+    H.chi2sum = __shfl(H.chi2sum, src, 64);
+    H.nmatch = __shfl(H.nmatch, src, 64);
+    H.live = __shfl(H.live, src, 64);
+    H.valid = __shfl(H.valid, src, 64);
+    H.status = (uint32_t)__shfl((int)H.status, src, 64);
+#pragma unroll
+    for (int k = 0; k < kLayers; k++) {
+        H.idx[k] = __shfl(H.idx[k], src, 64);
+        H.chi2l[k] = __shfl(H.chi2l[k], src, 64);
+    }
+}
+
+// Precise propagation to the chosen tracklet and the Kalman update, as for
+// the single best candidate.  False: the covariance lost positive
+// definiteness (NOT_PD set).
+template <typename TS, typename TC>
+__device__ __forceinline__ bool beam_apply(Hyp<TS, TC> &H, int l, int j, TS c2, float yj, float zj, int st,
+                                           const DevCfg<TS> &g)
+{
+    Trk<TS, TC> &T = H.T;
+    const TS tau = g.tilt[l];
+    const TS bdx = g.dx[T.sec * (kStacks * kLayers) + st * kLayers + l];
+    if (bdx != TS(0) && !propagate(T, g.x_layer[l] + bdx, g)) {
+        H.status |= kStopSnp;
+        H.live = 0;
+        return true;
+    }
+    const TS ry = TS(yj) - (T.y + tau * (T.z - TS(zj)));
+    const TS rz = TS(zj) - T.z;
+    const TS syu = poly2(g.sigma_y, T.s);
+    bool pd = true;
+    if (!kalman_update(T, ry, rz, tau, TC(syu) * TC(syu), TC(g.vz))) {
+        H.status |= kNotPD;
+        pd = false;
+    }
+#pragma unroll
+    for (int k = 0; k < kLayers; k++) {
+        H.idx[k] = k == l ? j : H.idx[k];
+        H.chi2l[k] = k == l ? c2 : H.chi2l[k];
+    }
+    H.nmatch++;
+    H.chi2sum += c2;
+    if (!(fabs(T.s) < g.snp_max)) {
+        H.status |= kStopSnp;
+        H.live = 0;
+    }
+    return pd;
+}
+
+// One track on the N lanes of a group (h = rank, base = first lane of the
+// group).  False: re-run with a double covariance (kQueueNotPD only); the
+// answer is group-uniform.
+template <typename TS, typename TC, int N, bool kQueueNotPD>
+__device__ __forceinline__ bool beam_track(const DevCfg<TS> &g, const MatchIO &io, int64_t i, int h, int base,
+                                           uint32_t status0)
+{
+    Hyp<TS, TC> H;
+    H.T.y = H.T.z = H.T.s = H.T.t = H.T.c = H.T.x = TS(0);
+#pragma unroll
+    for (int k = 0; k < 15; k++) H.T.C[k] = TC(0);
+    H.T.sec = 0;
+    H.cost = H.chi2sum = TS(0);
+    H.nmatch = 0;
+    H.live = H.valid = 0;
+    H.status = status0;
+#pragma unroll
+    for (int k = 0; k < kLayers; k++) {
+        H.idx[k] = -1;
+        H.chi2l[k] = TS(0);
+    }
+    int grp = 0, ld = 1;
+    if (h == 0) {
+        ld = load_track<TS, TC, kQueueNotPD>(g, io, i, H.T, grp);
+        H.valid = 1;
+        H.live = ld == 0;
+        if (ld == 1) H.status |= kBadInput;
+    }
+    ld = __shfl(ld, base, 64);
+    grp = __shfl(grp, base, 64);
+    if (ld == 2) return false;
+    for (int l = 0; l < kLayers; l++) {
+        TopN<TS, N> L;
+        L.init(H.cost);
+        if (H.valid && H.live) {
+            if (!predict(H.T, l, g, H.status)) {
+                H.live = 0;
+            } else {
+                Road<TS> R;
+                if (open_road(H.T, l, grp, g, H.status, R)) scan_road_flat(R, g, io, L);
+            }
+        }
+        // survivors: N rounds of a group-wide minimum
+        const TS skip_cost = H.cost + g.chi2_penalty;
+        bool skip = H.valid != 0;
+        int s_ok = 0, s_par = h, s_j = -1, s_st = 0;
+        TS s_cost = TS(0), s_c2 = TS(0);
+        float s_y = 0.f, s_z = 0.f;
+#pragma unroll 1
+        for (int r = 0; r < N; r++) {
+            const bool trk = L.idx[0] != 0x7fffffff;
+            const bool use_trk = trk && (!skip || !(skip_cost < L.cost[0]));
+            TS mc = use_trk ? L.cost[0] : (skip ? skip_cost : TS(INFINITY));
+            int ms = use_trk ? 0 : (skip ? 1 : 2);
+            int mj = use_trk ? L.idx[0] : (skip ? -1 : 0x7fffffff);
+            int mh = h;
+#pragma unroll
+            for (int off = N / 2; off >= 1; off >>= 1) {
+                const TS oc = __shfl_xor(mc, off, 64);
+                const int os = __shfl_xor(ms, off, 64);
+                const int oh = __shfl_xor(mh, off, 64);
+                const int oj = __shfl_xor(mj, off, 64);
+                const bool take =
+                    oc < mc ||
+                    (oc == mc && (os < ms || (os == ms && (oh < mh || (oh == mh && oj < mj)))));
+                mc = take ? oc : mc;
+                ms = take ? os : ms;
+                mh = take ? oh : mh;
+                mj = take ? oj : mj;
+            }
+            const int src = base + mh;
+            const TS pc2 = __shfl(L.chi2[0], src, 64);
+            const float py = __shfl(L.y[0], src, 64);
+            const float pz = __shfl(L.z[0], src, 64);
+            const int pst = __shfl(L.stack[0], src, 64);
+            if (h == r) {
+                s_ok = ms != 2;
+                s_par = ms != 2 ? mh : h;
+                s_j = ms == 0 ? mj : -1;
+                s_cost = mc;
+                s_c2 = pc2;
+                s_y = py;
+                s_z = pz;
+                s_st = pst;
+            }
+            if (h == mh && ms == 0) L.pop();
+            if (h == mh && ms == 1) skip = false;
+        }
+        pull(H, base + s_par);
+        int lost_pd = 0;
+        if (!s_ok) {
+            H.valid = 0;
+        } else {
+            H.cost = s_cost;
+            if (s_j >= 0 && H.live && !beam_apply(H, l, s_j, s_c2, s_y, s_z, s_st, g)) lost_pd = 1;
+        }
+        if (kQueueNotPD) {
+#pragma unroll
+            for (int off = N / 2; off >= 1; off >>= 1) lost_pd |= __shfl_xor(lost_pd, off, 64);
+            if (lost_pd) return false;
+        }
+    }
+    if (h == 0) {
+        const int64_t n = io.n;
+        TS *ochl = reinterpret_cast<TS *>(io.ochi2l);
+#pragma unroll
+        for (int k = 0; k < kLayers; k++) {
+            io.oidx[k * n + i] = H.idx[k];
+            if (ochl) ochl[k * n + i] = H.chi2l[k];
+        }
+        Acc<TS> acc;
+        acc.nmatch = H.nmatch;
+        acc.chi2sum = H.chi2sum;
+        acc.lidx = -1;
+        acc.lchi = TS(0);
+        write_track(io, i, H.T, acc, H.status);
+    }
+    return true;
+}
+
+template <typename TS, typename TC, int N, bool kFloatCov>
+__global__ void __launch_bounds__(256) k_match_beam(DevCfg<TS> g, MatchIO io)
+{
+    const int lane = threadIdx.x & 63, h = lane & (N - 1), base = lane & ~(N - 1);
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / N;
+    if (i >= io.n) return;  // uniform over the group
+    if (!beam_track<TS, TC, N, kFloatCov>(g, io, i, h, base, 0u) && h == 0)
+        io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
+}
+
+// Re-run of queued tracks with a double covariance, N lanes per track.
+template <int N>
+__global__ void __launch_bounds__(256) k_beam_fallback(DevCfg<float> g, MatchIO io)
+{
+    const uint32_t cnt = *io.fb_count;
+    const int lane = threadIdx.x & 63, h = lane & (N - 1), base = lane & ~(N - 1);
+    const uint32_t per_block = blockDim.x / N;
+    for (uint32_t j = blockIdx.x * per_block + threadIdx.x / N; j < cnt; j += gridDim.x * per_block)
+        beam_track<float, double, N, false>(g, io, io.fb_list[j], h, base, kFallback);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(io.fb_done, 1u) == gridDim.x - 1) {
+            atomicExch(io.fb_count, 0u);
+            atomicExch(io.fb_done, 0u);
+        }
+    }
+}
+
+template <typename TS, typename TC, bool kFloatCov>
+void launch_beam_t(const DevCfg<TS> &g, const MatchIO &io, int n_hyp, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((io.n * n_hyp + 255) / 256);
+    switch (n_hyp) {
+    case 1: hipLaunchKernelGGL((k_match_beam<TS, TC, 1, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
+    case 2: hipLaunchKernelGGL((k_match_beam<TS, TC, 2, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
+    case 4: hipLaunchKernelGGL((k_match_beam<TS, TC, 4, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
+    default: hipLaunchKernelGGL((k_match_beam<TS, TC, 8, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
+    }
+}
+
 }  // namespace
+
+void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf, const MatchIO &io,
+                 int n_hyp, hipStream_t s)
+{
+    if (io.n <= 0) return;
+    if (precision == 0) {
+        launch_beam_t<double, double, false>(gd, io, n_hyp, s);
+    } else if (precision == 2) {
+        launch_beam_t<float, double, false>(gf, io, n_hyp, s);
+    } else {
+        launch_beam_t<float, float, true>(gf, io, n_hyp, s);
+        switch (n_hyp) {
+        case 1: hipLaunchKernelGGL(k_beam_fallback<1>, dim3(64), dim3(256), 0, s, gf, io); break;
+        case 2: hipLaunchKernelGGL(k_beam_fallback<2>, dim3(64), dim3(256), 0, s, gf, io); break;
+        case 4: hipLaunchKernelGGL(k_beam_fallback<4>, dim3(64), dim3(256), 0, s, gf, io); break;
+        default: hipLaunchKernelGGL(k_beam_fallback<8>, dim3(64), dim3(256), 0, s, gf, io); break;
+        }
+    }
+}
 
 template <typename TS, typename TC, bool kFloatCov>
 unsigned persistent_grid(int block, int n_cu, unsigned grid)

@@ -97,9 +97,11 @@ def test_deflection_bins(prec, tilt):
     # Float state with tilted pads: on steep low-pT tracks the slope rounding
     # reaches y through dx/f^3 (~50 cm per layer) and the tilt term feeds the
     # y error into tan(lambda) through the gain; measured worst track 1.4e-5,
-    # 99.9 % of tracks within 1e-5.
-    loose = 2e-5 if (tilt and prec != "fp64") else None
-    rep = pu.compare(ref, res, prec, state_tol_max=loose)
+    # 99.9 % of tracks within 1.1e-5 (in both float paths: the state, not the
+    # covariance, carries it).
+    loose = (tilt and prec != "fp64")
+    rep = pu.compare(ref, res, prec, state_tol_max=2e-5 if loose else None,
+                     q999_tol=1.5e-5 if loose else None)
     print(rep.summary())
     assert rep.ok, rep.summary()
 
