@@ -69,6 +69,11 @@ extern "C" {
 #define TRD_CFG_FAIL_ALLOC 1u     /* test hook: trd_create fails with TRD_ENOMEM */
 #define TRD_CFG_FORCE_FALLBACK 2u /* test hook (TRD_PREC_FP32): every track takes the
                                      double-covariance re-run */
+#define TRD_CFG_INPUT_ORDER 8u    /* match the tracks in the caller's order; by default
+                                     the one-lane-per-track launch first sorts them by
+                                     (group, sector, z, y) of the seed so that neighbouring
+                                     lanes read neighbouring cells (results are the same,
+                                     bit for bit, and come back in input order) */
 #define TRD_CFG_PERSISTENT 4u     /* one-lane-per-track matching as a persistent grid
                                      (resident workgroups pull blocks of tracks from a
                                      work counter); for large multi-frame batches.

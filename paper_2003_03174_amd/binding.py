@@ -22,6 +22,7 @@ TRK_STOP_SNP, TRK_ROT_FAIL, TRK_OUT_OF_Z, TRK_FP64_FALLBACK, TRK_NOT_PD, TRK_BAD
 TRD_CFG_FAIL_ALLOC = 1
 TRD_CFG_FORCE_FALLBACK = 2
 TRD_CFG_PERSISTENT = 4
+TRD_CFG_INPUT_ORDER = 8
 
 # every symbol include/trd.h declares
 EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_get_binning",

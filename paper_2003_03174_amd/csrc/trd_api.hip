@@ -32,6 +32,10 @@ struct trd_ctx {
     // track-side capacity
     int64_t cap_trk = 0;
     int32_t *d_fb = nullptr;
+    // processing order of the tracks (spatial sort) and the state rows in it
+    uint32_t *d_tkey_a = nullptr, *d_tkey_b = nullptr, *d_tval_a = nullptr, *d_tval_b = nullptr;
+    uint32_t *d_trank = nullptr, *d_thist = nullptr, *d_thist_off = nullptr, *d_ttiles = nullptr;
+    unsigned char *d_rows_in = nullptr, *d_rows_out = nullptr;
 
     int64_t bytes = 0;
     bool loaded = false;
@@ -164,7 +168,23 @@ int64_t tkl_bytes(int64_t n)
     return m * (4 + 4 + 16 + 16) + 8 * hist_len(n) + 4 * scan_block_sums_len(hist_len(n));
 }
 int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1) + 4 * scan_block_sums_len(nc + 1); }
-int64_t trk_bytes(int64_t n) { return 4 * (n > 0 ? n : 1); }
+// tracks are matched in a spatial order (rows of state in, rows of results
+// out) unless the caller keeps its own order or the launch shape has no use
+// for it (several lanes per road, several hypotheses)
+bool ordered(const trd_config &c)
+{
+    return !(c.flags & TRD_CFG_INPUT_ORDER) && c.search_lanes <= 1 && c.n_hyp == 0;
+}
+int64_t row_scalar(const trd_config &c) { return c.precision == TRD_PREC_FP64 ? 8 : 4; }
+int64_t trk_bytes(const trd_config &c, int64_t n)
+{
+    const int64_t m = n > 0 ? n : 1;
+    int64_t b = 4 * m;
+    if (ordered(c))
+        b += m * (20 + (kRowIn + kRowOut) * row_scalar(c)) + 8 * hist_len(m) +
+             4 * scan_block_sums_len(hist_len(m));
+    return b;
+}
 
 int over_budget(const trd_ctx *ctx, int64_t extra)
 {
@@ -232,22 +252,51 @@ int ensure_cells(trd_ctx *ctx, int64_t nc)
     return TRD_OK;
 }
 
+void free_trk(trd_ctx *ctx)
+{
+    dev_free(&ctx->d_fb);
+    dev_free(&ctx->d_tkey_a);
+    dev_free(&ctx->d_tkey_b);
+    dev_free(&ctx->d_tval_a);
+    dev_free(&ctx->d_tval_b);
+    dev_free(&ctx->d_trank);
+    dev_free(&ctx->d_thist);
+    dev_free(&ctx->d_thist_off);
+    dev_free(&ctx->d_ttiles);
+    dev_free(&ctx->d_rows_in);
+    dev_free(&ctx->d_rows_out);
+}
+
 int ensure_trk(trd_ctx *ctx, int64_t n)
 {
     if (n <= ctx->cap_trk && ctx->d_fb) return TRD_OK;
+    const trd_config &c = ctx->cfg;
     int64_t cap = n > 2 * ctx->cap_trk ? n : 2 * ctx->cap_trk;
-    const int64_t old = ctx->d_fb ? trk_bytes(ctx->cap_trk) : 0;
-    if (over_budget(ctx, trk_bytes(cap) - old)) {
+    const int64_t old = ctx->d_fb ? trk_bytes(c, ctx->cap_trk) : 0;
+    if (over_budget(ctx, trk_bytes(c, cap) - old)) {
         cap = n;
-        if (over_budget(ctx, trk_bytes(cap) - old)) return TRD_EBUDGET;
+        if (over_budget(ctx, trk_bytes(c, cap) - old)) return TRD_EBUDGET;
     }
-    dev_free(&ctx->d_fb);
+    free_trk(ctx);
     ctx->bytes -= old;
     ctx->cap_trk = 0;
     int64_t acc = 0;
     int rc = dev_alloc(ctx, &ctx->d_fb, cap, &acc);
-    if (rc) return rc;
-    ctx->bytes += trk_bytes(cap);
+    if (!rc && ordered(c)) {
+        const int64_t hl = hist_len(cap), rs = row_scalar(c);
+        (void)((rc = dev_alloc(ctx, &ctx->d_tkey_a, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_tkey_b, cap, &acc)) ||
+               (rc = dev_alloc(ctx, &ctx->d_tval_a, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_tval_b, cap, &acc)) ||
+               (rc = dev_alloc(ctx, &ctx->d_trank, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_thist, hl, &acc)) ||
+               (rc = dev_alloc(ctx, &ctx->d_thist_off, hl, &acc)) ||
+               (rc = dev_alloc(ctx, &ctx->d_ttiles, scan_block_sums_len(hl), &acc)) ||
+               (rc = dev_alloc(ctx, &ctx->d_rows_in, cap * kRowIn * rs, &acc)) ||
+               (rc = dev_alloc(ctx, &ctx->d_rows_out, cap * kRowOut * rs, &acc)));
+    }
+    if (rc) {
+        free_trk(ctx);
+        return rc;
+    }
+    ctx->bytes += trk_bytes(c, cap);
     ctx->cap_trk = cap;
     return TRD_OK;
 }
@@ -372,7 +421,8 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
         return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
     int rc;
-    if (ctx->cfg.precision == TRD_PREC_FP32 && (rc = ensure_trk(ctx, n))) return rc;
+    const bool ord = ordered(ctx->cfg) && ctx->n_groups < kMaxOrderGroups;
+    if ((ctx->cfg.precision == TRD_PREC_FP32 || ordered(ctx->cfg)) && (rc = ensure_trk(ctx, n))) return rc;
     MatchIO io{};
     io.sorted = ctx->d_sorted;
     io.offsets = ctx->d_offsets;
@@ -397,12 +447,20 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
     io.work_next = ctx->d_small + 2;
     io.work_done = ctx->d_small + 3;
-    if (ctx->cfg.n_hyp > 0)
-        launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, (hipStream_t)hip_stream);
-    else
-        launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size,
-                     ctx->cfg.search_lanes, (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu,
-                     (hipStream_t)hip_stream);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if (ctx->cfg.n_hyp > 0) {
+        launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, s);
+        return launch_status();
+    }
+    TrackOrder ord_buf{};
+    if (ord) {
+        ord_buf = TrackOrder{ctx->d_tkey_a, ctx->d_tkey_b, ctx->d_tval_a, ctx->d_tval_b, ctx->d_trank,
+                             ctx->d_thist, ctx->d_thist_off, ctx->d_ttiles, ctx->d_rows_in, ctx->d_rows_out};
+        launch_order_in(ctx->cfg.precision, io, ctx->n_groups, ord_buf, s);
+    }
+    launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size, ctx->cfg.search_lanes,
+                 (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu, s);
+    if (ord) launch_order_out(ctx->cfg.precision, io, ord_buf, s);
     return launch_status();
 }
 
@@ -447,7 +505,7 @@ void trd_destroy(trd_ctx *ctx)
     free_tkl(ctx);
     dev_free(&ctx->d_offsets);
     dev_free(&ctx->d_tiles_cell);
-    dev_free(&ctx->d_fb);
+    free_trk(ctx);
     delete ctx;
 }
 

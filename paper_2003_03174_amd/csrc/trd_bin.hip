@@ -78,38 +78,63 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
     return off + incl - v;
 }
 
-// Source of the radix passes: the caller's tracklet arrays on the first
-// pass (key computed on the fly), the previous pass's output afterwards.
-struct RadixSrc {
+// Sources of the radix passes.  First pass of the tracklet sort: the
+// caller's arrays, key and record computed on the fly.  Later passes (and
+// any sort of precomputed keys): the previous pass's keys and records.
+struct TklSrc {
     const float *y, *z, *dy;
     const uint32_t *det_row;
     const int32_t *grp;
-    const uint32_t *keys;  // null on the first pass
-    const float4 *recs;
+    BinCfg b;
+    using Rec = float4;
+    __device__ __forceinline__ uint32_t key(int64_t e) const
+    {
+        return cell_key(y[e], z[e], dy[e], det_row[e], grp ? grp[e] : 0, b);
+    }
+    __device__ __forceinline__ void load(int64_t e, uint32_t &k, float4 &rec) const
+    {
+        const float ye = y[e], ze = z[e], dye = dy[e];
+        k = cell_key(ye, ze, dye, det_row[e], grp ? grp[e] : 0, b);
+        rec = make_float4(ye, dye, ze, __int_as_float((int)e));
+    }
 };
 
-__device__ __forceinline__ void radix_load(const RadixSrc &src, const BinCfg &b, int64_t e,
-                                           uint32_t &key, float4 &rec)
-{
-    if (src.keys) {
-        key = src.keys[e];
-        rec = src.recs[e];
-    } else {
-        const float y = src.y[e], z = src.z[e], dy = src.dy[e];
-        key = cell_key(y, z, dy, src.det_row[e], src.grp ? src.grp[e] : 0, b);
-        rec = make_float4(y, dy, z, __int_as_float((int)e));
+// First pass of the track sort: the seed's order key, its index as value.
+template <typename TS>
+struct TrkSrc {
+    const TS *ip;
+    const int32_t *isec, *igrp;
+    int64_t n;
+    int32_t n_groups;
+    using Rec = uint32_t;
+    __device__ __forceinline__ uint32_t key(int64_t e) const
+    {
+        return track_order_key(ip[e], ip[n + e], isec[e], igrp ? igrp[e] : 0, n_groups);
     }
-}
+    __device__ __forceinline__ void load(int64_t e, uint32_t &k, uint32_t &rec) const
+    {
+        k = key(e);
+        rec = (uint32_t)e;
+    }
+};
 
-__device__ __forceinline__ uint32_t radix_key_only(const RadixSrc &src, const BinCfg &b, int64_t e)
-{
-    if (src.keys) return src.keys[e];
-    return cell_key(src.y[e], src.z[e], src.dy[e], src.det_row[e], src.grp ? src.grp[e] : 0, b);
-}
+template <typename R>
+struct PassSrc {
+    const uint32_t *keys;
+    const R *recs;
+    using Rec = R;
+    __device__ __forceinline__ uint32_t key(int64_t e) const { return keys[e]; }
+    __device__ __forceinline__ void load(int64_t e, uint32_t &k, R &rec) const
+    {
+        k = keys[e];
+        rec = recs[e];
+    }
+};
 
 // digit histogram of one tile, stored digit-major: hist[d * n_blocks + block]
+template <typename Src>
 __global__ void __launch_bounds__(kBlock)
-    k_radix_hist(RadixSrc src, BinCfg b, int64_t n, int shift, uint32_t *__restrict__ hist)
+    k_radix_hist(Src src, int64_t n, int shift, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[kBins];
     h[threadIdx.x] = 0;
@@ -118,7 +143,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
         const int64_t e = base + j * kBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(radix_key_only(src, b, e) >> shift) & (kBins - 1)], 1u);
+        if (e < n) atomicAdd(&h[(src.key(e) >> shift) & (kBins - 1)], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -129,17 +154,19 @@ __global__ void __launch_bounds__(kBlock)
 // from eight ballots, the counts of earlier wavefronts and sub-tiles from LDS.
 // The tile is first regrouped by digit in LDS, so that each digit's run goes
 // out as contiguous stores.
+template <typename Src>
 __global__ void __launch_bounds__(kBlock)
-    k_radix_scatter(RadixSrc src, BinCfg b, int64_t n, int shift, const uint32_t *__restrict__ hist,
+    k_radix_scatter(Src src, int64_t n, int shift, const uint32_t *__restrict__ hist,
                     const uint32_t *__restrict__ hist_off, uint32_t *__restrict__ keys_out,
-                    float4 *__restrict__ recs_out)
+                    typename Src::Rec *__restrict__ recs_out, uint32_t *__restrict__ rank_out)
 {
+    using Rec = typename Src::Rec;
     __shared__ uint32_t run[kBins];      // elements of each digit placed so far in this tile
     __shared__ uint32_t loc[kBins];      // first LDS slot of each digit in this tile
     __shared__ uint32_t glob[kBins];     // first global position of each digit for this tile
     __shared__ uint32_t wcnt[kBlock / 64][kBins];
     __shared__ uint32_t skey[kSortTile];
-    __shared__ float4 srec[kSortTile];
+    __shared__ Rec srec[kSortTile];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t cnt = hist[(int64_t)tid * gridDim.x + blockIdx.x];
     uint32_t tot;
@@ -155,8 +182,8 @@ __global__ void __launch_bounds__(kBlock)
         const int64_t e = base + j * kBlock + tid;
         const bool valid = e < n;
         uint32_t key = 0;
-        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (valid) radix_load(src, b, e, key, rec);
+        Rec rec{};
+        if (valid) src.load(e, key, rec);
         const uint32_t d = (key >> shift) & (kBins - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -191,6 +218,9 @@ __global__ void __launch_bounds__(kBlock)
         const uint32_t pos = glob[d] + (uint32_t)p - loc[d];
         keys_out[pos] = key;
         recs_out[pos] = srec[p];
+        // last pass of an index sort: where each index ended up
+        if constexpr (sizeof(Rec) == 4)
+            if (rank_out) rank_out[srec[p]] = pos;
     }
 }
 
@@ -423,6 +453,26 @@ static void launch_suffix_min(uint32_t *a, int64_t n, uint32_t *tiles, hipStream
     hipLaunchKernelGGL(k_min_down, dim3((unsigned)nb), dim3(kBlock), 0, s, a, n, tiles);
 }
 
+// One radix pass from src into (keys_out, recs_out).
+template <typename Src>
+static void radix_pass(const Src &src, int64_t n, int shift, uint32_t *hist, uint32_t *hist_off,
+                       uint32_t *tiles, uint32_t *keys_out, typename Src::Rec *recs_out, hipStream_t s,
+                       uint32_t *rank_out = nullptr)
+{
+    const int64_t nblk = radix_blocks(n);
+    hipLaunchKernelGGL(k_radix_hist<Src>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift, hist);
+    launch_excl_scan(hist, nblk * kBins, tiles, hist_off, s);
+    hipLaunchKernelGGL(k_radix_scatter<Src>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift, hist,
+                       hist_off, keys_out, recs_out, rank_out);
+}
+
+static int radix_passes(uint64_t max_key)
+{
+    int bits = 1;
+    while (bits < 32 && max_key >> bits) bits++;
+    return (bits + kRadixBits - 1) / kRadixBits;
+}
+
 void launch_bin(const float *y, const float *z, const float *dy, const uint32_t *det_row,
                 const int32_t *grp, int64_t n, const BinCfg &b, BinBuffers &buf, hipStream_t s)
 {
@@ -431,24 +481,18 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
     launch_fill_u32(buf.offsets, 0xffffffffu, nc, s);
     launch_fill_u32(buf.offsets + nc, (uint32_t)n, 1, s);
     if (n > 0) {
-        int bits = 1;
-        while (bits < 32 && (uint64_t)nc >> bits) bits++;
-        const int passes = (bits + kRadixBits - 1) / kRadixBits;
-        const int64_t nblk = radix_blocks(n);
+        const int passes = radix_passes((uint64_t)nc);
         // ping-pong so that the last pass lands in buf.sorted
         uint32_t *kdst[2] = {buf.keys_a, buf.keys_b};
         float4 *rdst[2] = {buf.sorted, buf.recs_tmp};
         int out = (passes % 2 == 1) ? 0 : 1;
-        RadixSrc src{y, z, dy, det_row, grp, nullptr, nullptr};
-        for (int p = 0; p < passes; p++) {
-            const int shift = p * kRadixBits;
-            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, b, n, shift,
-                               buf.hist);
-            launch_excl_scan(buf.hist, nblk * kBins, buf.tiles_tkl, buf.hist_off, s);
-            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, b, n, shift,
-                               buf.hist, buf.hist_off, kdst[out], rdst[out]);
-            src.keys = kdst[out];
-            src.recs = rdst[out];
+        radix_pass(TklSrc{y, z, dy, det_row, grp, b}, n, 0, buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
+                   rdst[out], s);
+        PassSrc<float4> src{kdst[out], rdst[out]};
+        out ^= 1;
+        for (int p = 1; p < passes; p++) {
+            radix_pass(src, n, p * kRadixBits, buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out], rdst[out], s);
+            src = PassSrc<float4>{kdst[out], rdst[out]};
             out ^= 1;
         }
         hipLaunchKernelGGL(k_run_starts, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src.keys, n,
@@ -456,6 +500,33 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
         buf.sorted_keys = src.keys;
     }
     launch_suffix_min(buf.offsets, nc + 1, buf.tiles_cell, s);
+}
+
+template <typename TS>
+static void track_sort(const TS *ip, const int32_t *isec, const int32_t *igrp, int64_t n, int32_t n_groups,
+                       const TrackOrder &o, hipStream_t s)
+{
+    const int passes = radix_passes((uint64_t)(n_groups * kSectors) << kOrderPosBits);
+    uint32_t *kb[2] = {o.key_a, o.key_b};
+    uint32_t *vb[2] = {o.val_a, o.val_b};
+    radix_pass(TrkSrc<TS>{ip, isec, igrp, n, n_groups}, n, 0, o.hist, o.hist_off, o.tiles, kb[0], vb[0], s,
+               passes == 1 ? o.rank : nullptr);
+    int cur = 0;
+    for (int p = 1; p < passes; p++) {
+        radix_pass(PassSrc<uint32_t>{kb[cur], vb[cur]}, n, p * kRadixBits, o.hist, o.hist_off, o.tiles,
+                   kb[cur ^ 1], vb[cur ^ 1], s, p == passes - 1 ? o.rank : nullptr);
+        cur ^= 1;
+    }
+}
+
+void launch_track_sort(int precision, const void *ip, const int32_t *isec, const int32_t *igrp, int64_t n,
+                       int32_t n_groups, const TrackOrder &o, hipStream_t s)
+{
+    if (n <= 0) return;
+    if (precision == 0)
+        track_sort(static_cast<const double *>(ip), isec, igrp, n, n_groups, o, s);
+    else
+        track_sort(static_cast<const float *>(ip), isec, igrp, n, n_groups, o, s);
 }
 
 }  // namespace trd

@@ -81,7 +81,59 @@ struct MatchIO {
     int force_fallback;  // test hook: queue every track for the re-run
     uint32_t *work_next; // [1] persistent launch: next block of tracks
     uint32_t *work_done; // [1] persistent launch: finished workgroups
+    // Ordered mode (both set): track i of the launch is row i of rows_in and
+    // its results go to row i of rows_out, instead of the caller's arrays.
+    const void *rows_in;  // [n][kRowIn] of the state type
+    void *rows_out;       // [n][kRowOut] of the state type
+    int row_out;  // entries per result row: kRowOut, or kRowOutShort without chi2 per layer
 };
+
+// Rows of the ordered mode, in units of the state type.
+// in:  p[5], cov[15], x, sector, group (integers stored bit-exact), pad
+// out: p[5], cov[15], x, chi2, sector, n_match, status, idx[6], pad, chi2[6], pad
+constexpr int kRowIn = 24;
+constexpr int kRowOut = 40;
+constexpr int kRowOutShort = 32;  // without the chi2 per layer
+constexpr int kRowChi2 = 32;      // first chi2-per-layer entry of a long row
+// the order key holds the group and sector above 11 position bits
+constexpr int kOrderPosBits = 11;
+constexpr int32_t kMaxOrderGroups = (1 << (32 - kOrderPosBits)) / kSectors;
+
+// Processing-order key of a seed: group and sector, then 16 cm in z and 4 cm
+// in y (clamped); rejected seeds get the largest key.
+template <typename TS>
+__device__ __forceinline__ uint32_t track_order_key(TS y, TS z, int sec, int grp, int32_t n_groups)
+{
+    uint32_t k = (uint32_t)(n_groups * kSectors) << kOrderPosBits;
+    if (sec >= 0 && sec < kSectors && grp >= 0 && grp < n_groups && __builtin_isfinite(y) &&
+        __builtin_isfinite(z)) {
+        const TS zs = (z + TS(512)) * TS(0.0625), ys = (y + TS(64)) * TS(0.25);
+        const int zb = zs < TS(0) ? 0 : (zs >= TS(63) ? 63 : (int)zs);
+        const int yb = ys < TS(0) ? 0 : (ys >= TS(31) ? 31 : (int)ys);
+        k = ((uint32_t)(grp * kSectors + sec) << kOrderPosBits) | ((uint32_t)zb << 5) | (uint32_t)yb;
+    }
+    return k;
+}
+
+// buffers of the spatial track order (capacity n each unless noted)
+struct TrackOrder {
+    uint32_t *key_a, *key_b, *val_a, *val_b;  // sort ping-pong
+    uint32_t *rank;                           // rank[i]: row of input track i
+    uint32_t *hist, *hist_off, *tiles;        // radix_blocks(n) * 256, its scan tiles
+    void *rows_in, *rows_out;
+};
+
+// Stable sort of the seeds by track_order_key (state of type double for
+// precision 0, float otherwise, p component-major as in the C ABI); fills
+// o.rank.  Overwrites key_a/b, val_a/b, hist, hist_off, tiles.
+void launch_track_sort(int precision, const void *ip, const int32_t *isec, const int32_t *igrp, int64_t n,
+                       int32_t n_groups, const TrackOrder &o, hipStream_t s);
+
+// Sorts the tracks by (group, sector, z, y) of the seed, packs their state
+// into io.rows_in in that order and points io at the rows.
+void launch_order_in(int precision, MatchIO &io, int32_t n_groups, const TrackOrder &o, hipStream_t s);
+// Copies the result rows back to the caller's arrays in input order.
+void launch_order_out(int precision, const MatchIO &io, const TrackOrder &o, hipStream_t s);
 
 // precision: 0 = FP64, 1 = FP32 (+ fallback), 2 = FP32 state / FP64 covariance
 // lanes: lanes that scan one track's road together (1 = one lane per track)

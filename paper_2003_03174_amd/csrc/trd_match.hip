@@ -37,6 +37,12 @@ struct Trk {
 
 template <typename T> __device__ __forceinline__ T sq(T a) { return a * a; }
 
+// integers in rows of the state type: bit pattern in float, value in double
+__device__ __forceinline__ float as_row(int v, float) { return __int_as_float(v); }
+__device__ __forceinline__ double as_row(int v, double) { return (double)v; }
+__device__ __forceinline__ int int_of(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int int_of(double v) { return (int)v; }
+
 template <typename T> __device__ __forceinline__ T sinc_(T u) { return u == T(0) ? T(1) : sin(u) / u; }
 
 // (sin d - d) / d^2; Taylor series below |d| = 0.5 where the direct form cancels
@@ -341,20 +347,34 @@ template <typename TS, typename TC, bool kQueueNotPD>
 __device__ __forceinline__ int load_track(const DevCfg<TS> &g, const MatchIO &io, int64_t i,
                                           Trk<TS, TC> &T, int &grp)
 {
-    const int64_t n = io.n;
-    const TS *ip = reinterpret_cast<const TS *>(io.ip);
-    const TS *ic = reinterpret_cast<const TS *>(io.ic);
-    const TS *ix = reinterpret_cast<const TS *>(io.ix);
-    T.y = ip[i];
-    T.z = ip[n + i];
-    T.s = ip[2 * n + i];
-    T.t = ip[3 * n + i];
-    T.c = ip[4 * n + i];
-    T.x = ix[i];
+    if (io.rows_in) {
+        const TS *r = reinterpret_cast<const TS *>(io.rows_in) + i * kRowIn;
+        T.y = r[0];
+        T.z = r[1];
+        T.s = r[2];
+        T.t = r[3];
+        T.c = r[4];
 #pragma unroll
-    for (int k = 0; k < 15; k++) T.C[k] = TC(ic[k * n + i]);
-    T.sec = io.isec[i];
-    grp = io.igrp ? io.igrp[i] : 0;
+        for (int k = 0; k < 15; k++) T.C[k] = TC(r[5 + k]);
+        T.x = r[20];
+        T.sec = int_of(r[21]);
+        grp = int_of(r[22]);
+    } else {
+        const int64_t n = io.n;
+        const TS *ip = reinterpret_cast<const TS *>(io.ip);
+        const TS *ic = reinterpret_cast<const TS *>(io.ic);
+        const TS *ix = reinterpret_cast<const TS *>(io.ix);
+        T.y = ip[i];
+        T.z = ip[n + i];
+        T.s = ip[2 * n + i];
+        T.t = ip[3 * n + i];
+        T.c = ip[4 * n + i];
+        T.x = ix[i];
+#pragma unroll
+        for (int k = 0; k < 15; k++) T.C[k] = TC(ic[k * n + i]);
+        T.sec = io.isec[i];
+        grp = io.igrp ? io.igrp[i] : 0;
+    }
     bool bad = !(__builtin_isfinite(T.x) && T.sec >= 0 && T.sec < kSectors && grp >= 0 &&
                  grp < g.bin.n_groups);
     bad |= !(__builtin_isfinite(T.y) && __builtin_isfinite(T.z) && __builtin_isfinite(T.s) &&
@@ -710,6 +730,12 @@ __device__ __forceinline__ int apply_best(Trk<TS, TC> &T, int l, const Road<TS> 
 template <typename TS>
 __device__ __forceinline__ void write_layer(const MatchIO &io, int64_t i, int l, const Acc<TS> &acc)
 {
+    if (io.rows_out) {
+        TS *r = reinterpret_cast<TS *>(io.rows_out) + i * io.row_out;
+        r[25 + l] = as_row(acc.lidx, TS());
+        if (io.ochi2l) r[kRowChi2 + l] = acc.lchi;
+        return;
+    }
     io.oidx[l * io.n + i] = acc.lidx;
     if (io.ochi2l) reinterpret_cast<TS *>(io.ochi2l)[l * io.n + i] = acc.lchi;
 }
@@ -718,6 +744,22 @@ template <typename TS, typename TC>
 __device__ __forceinline__ void write_track(const MatchIO &io, int64_t i, const Trk<TS, TC> &T,
                                             const Acc<TS> &acc, uint32_t status)
 {
+    if (io.rows_out) {
+        TS *r = reinterpret_cast<TS *>(io.rows_out) + i * io.row_out;
+        r[0] = T.y;
+        r[1] = T.z;
+        r[2] = T.s;
+        r[3] = T.t;
+        r[4] = T.c;
+#pragma unroll
+        for (int k = 0; k < 15; k++) r[5 + k] = TS(T.C[k]);
+        r[20] = T.x;
+        r[21] = acc.chi2sum;
+        r[22] = as_row(T.sec, TS());
+        r[23] = as_row(acc.nmatch, TS());
+        r[24] = as_row((int)status, TS());
+        return;
+    }
     const int64_t n = io.n;
     TS *op = reinterpret_cast<TS *>(io.op);
     TS *oc = reinterpret_cast<TS *>(io.oc);
@@ -779,11 +821,28 @@ __device__ __forceinline__ bool match_lane(const DevCfg<TS> &g, const MatchIO &i
     return true;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b to XCD
+// b mod 8), each with its own L2.  Renumbering them so that XCD x runs the
+// x-th contiguous eighth of the tracks keeps neighbouring tracks (in the
+// spatial order: neighbouring cells) on one L2.  A bijection on
+// [0, gridDim.x) for any grid size.
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x, q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
+// Waves per SIMD the one-lane kernels are compiled for: four for the float
+// path (at most 128 registers; the road scan is latency bound, so the extra
+// waves in flight are worth a few spilled registers), the register need of
+// the double-covariance paths otherwise.
+template <typename TC> constexpr int kMinWaves = sizeof(TC) == 4 ? 4 : 1;
+
 // One lane per track (the plain kernel; double precision runs here).
 template <typename TS, typename TC, bool kFloatCov>
-__global__ void __launch_bounds__(256) k_match(DevCfg<TS> g, MatchIO io)
+__global__ void __launch_bounds__(256, kMinWaves<TC>) k_match(DevCfg<TS> g, MatchIO io)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (i >= io.n) return;
     if (!match_lane<TS, TC, kFloatCov>(g, io, i, 0u))
         io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
@@ -794,7 +853,7 @@ __global__ void __launch_bounds__(256) k_match(DevCfg<TS> g, MatchIO io)
 // (each workgroup exits once the counter passes the last block).  The last
 // workgroup to finish clears the counter for the next launch.
 template <typename TS, typename TC, bool kFloatCov>
-__global__ void __launch_bounds__(256) k_match_persistent(DevCfg<TS> g, MatchIO io)
+__global__ void __launch_bounds__(256, kMinWaves<TC>) k_match_persistent(DevCfg<TS> g, MatchIO io)
 {
     __shared__ uint32_t blk;
     const uint32_t nblk = (uint32_t)((io.n + blockDim.x - 1) / blockDim.x);
@@ -1266,6 +1325,110 @@ void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &g
         default: hipLaunchKernelGGL(k_beam_fallback<8>, dim3(64), dim3(256), 0, s, gf, io); break;
         }
     }
+}
+
+namespace {
+
+// input track i -> state row rank[i] (coalesced reads, one row per lane)
+template <typename TS>
+__global__ void __launch_bounds__(256) k_track_pack(MatchIO io, const uint32_t *rank, TS *rows)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= io.n) return;
+    const int64_t n = io.n;
+    const TS *ip = reinterpret_cast<const TS *>(io.ip);
+    const TS *ic = reinterpret_cast<const TS *>(io.ic);
+    const TS *ix = reinterpret_cast<const TS *>(io.ix);
+    TS v[kRowIn];
+#pragma unroll
+    for (int k = 0; k < 5; k++) v[k] = ip[k * n + i];
+#pragma unroll
+    for (int k = 0; k < 15; k++) v[5 + k] = ic[k * n + i];
+    v[20] = ix[i];
+    v[21] = as_row(io.isec[i], TS());
+    v[22] = as_row(io.igrp ? io.igrp[i] : 0, TS());
+    v[23] = TS(0);
+    TS *r = rows + (int64_t)rank[i] * kRowIn;
+#pragma unroll
+    for (int k = 0; k < kRowIn; k++) r[k] = v[k];
+}
+
+// result row rank[i] -> the caller's arrays at input position i
+template <typename TS, int kRow>
+__global__ void __launch_bounds__(256) k_track_unpack(MatchIO io, const uint32_t *rank, const TS *rows)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= io.n) return;
+    const int64_t n = io.n;
+    const TS *r = rows + (int64_t)rank[i] * kRow;
+    TS v[kRow];
+#pragma unroll
+    for (int k = 0; k < kRow; k++) v[k] = r[k];
+    TS *op = reinterpret_cast<TS *>(io.op);
+    TS *oc = reinterpret_cast<TS *>(io.oc);
+    TS *ox = reinterpret_cast<TS *>(io.ox);
+    TS *och = reinterpret_cast<TS *>(io.ochi2);
+#pragma unroll
+    for (int k = 0; k < 5; k++) op[k * n + i] = v[k];
+#pragma unroll
+    for (int k = 0; k < 15; k++) oc[k * n + i] = v[5 + k];
+    ox[i] = v[20];
+    och[i] = v[21];
+    io.osec[i] = int_of(v[22]);
+    io.onm[i] = int_of(v[23]);
+    io.ost[i] = (uint32_t)int_of(v[24]);
+#pragma unroll
+    for (int l = 0; l < kLayers; l++) io.oidx[l * n + i] = int_of(v[25 + l]);
+    if constexpr (kRow > kRowChi2) {
+        TS *ochl = reinterpret_cast<TS *>(io.ochi2l);
+#pragma unroll
+        for (int l = 0; l < kLayers; l++) ochl[l * n + i] = v[kRowChi2 + l];
+    }
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename TS>
+void order_in(MatchIO &io, int32_t n_groups, const TrackOrder &o, hipStream_t s)
+{
+    const int64_t n = io.n;
+    launch_track_sort(sizeof(TS) == 8 ? 0 : 1, io.ip, io.isec, io.igrp, n, n_groups, o, s);
+    hipLaunchKernelGGL(k_track_pack<TS>, dim3(blocks_for(n)), dim3(256), 0, s, io, (const uint32_t *)o.rank,
+                       reinterpret_cast<TS *>(o.rows_in));
+    io.rows_in = o.rows_in;
+    io.rows_out = o.rows_out;
+    io.row_out = io.ochi2l ? kRowOut : kRowOutShort;
+}
+
+template <typename TS>
+void order_out(const MatchIO &io, const TrackOrder &o, hipStream_t s)
+{
+    if (io.row_out == kRowOut)
+        hipLaunchKernelGGL((k_track_unpack<TS, kRowOut>), dim3(blocks_for(io.n)), dim3(256), 0, s, io,
+                           (const uint32_t *)o.rank, reinterpret_cast<const TS *>(o.rows_out));
+    else
+        hipLaunchKernelGGL((k_track_unpack<TS, kRowOutShort>), dim3(blocks_for(io.n)), dim3(256), 0, s, io,
+                           (const uint32_t *)o.rank, reinterpret_cast<const TS *>(o.rows_out));
+}
+
+}  // namespace
+
+void launch_order_in(int precision, MatchIO &io, int32_t n_groups, const TrackOrder &o, hipStream_t s)
+{
+    if (io.n <= 0) return;
+    if (precision == 0)
+        order_in<double>(io, n_groups, o, s);
+    else
+        order_in<float>(io, n_groups, o, s);
+}
+
+void launch_order_out(int precision, const MatchIO &io, const TrackOrder &o, hipStream_t s)
+{
+    if (io.n <= 0) return;
+    if (precision == 0)
+        order_out<double>(io, o, s);
+    else
+        order_out<float>(io, o, s);
 }
 
 template <typename TS, typename TC, bool kFloatCov>

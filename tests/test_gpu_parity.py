@@ -286,3 +286,26 @@ def test_persistent_grid_agrees(prec):
             for k in ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status"):
                 assert np.array_equal(o[k], base[k], equal_nan=True), (bs, call, k)
         m.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
+def test_spatial_track_order_is_invisible(prec):
+    """The default launch matches the tracks in a spatial order (rows of state
+    in, rows of results out); results must be bit-identical to the caller's
+    order, here on several frames with rejected seeds and forced re-runs."""
+    w = synth.generate_frames(5, 4, [3000, 1, 2500, 900], [0.5] * 4,
+                              params_over=dict(y_bin_w=8.0, n_yb=16), ineff_frac=0.1)
+    w = dict(w)
+    w["p"] = w["p"].copy()
+    w["sector"] = w["sector"].copy()
+    w["p"][0, 7] = np.nan
+    w["sector"][11] = 40
+    flags = [0, B.TRD_CFG_FORCE_FALLBACK] if prec == "fp32" else [0]
+    for f in flags:
+        a = run_gpu(w, prec, flags=f)
+        b = run_gpu(w, prec, flags=f | B.TRD_CFG_INPUT_ORDER)
+        for k in ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), (f, k)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
+    rep = pu.compare(ref, a, prec)
+    assert rep.ok, rep.summary()
