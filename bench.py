@@ -8,9 +8,11 @@ already resident in device memory.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -18,6 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "k_match_c5_distortion_450k_fp32.md")
+SOURCES = ("trd_api.hip", "trd_bin.hip", "trd_match.hip", "trd_internal.h")
 
 
 def log(*a):
@@ -39,6 +43,29 @@ def bin_alg_bytes(n_tkl, n_cells):
     return n_tkl * (20 + 20 + 16) + n_cells * 16
 
 
+def source_hash():
+    """sha256 of the HIP sources the library is built from."""
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(os.path.join(ROOT, "paper_2003_03174_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch of k_match from the committed counter summary, if
+    it was taken on the current sources (else None)."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    s = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not s or s.group(1) != source_hash():
+        return None
+    return float(m.group(1))
+
+
 def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None, flags=0):
     import torch
     from paper_2003_03174_amd import binding as B
@@ -47,6 +74,8 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
     if d is None:
         d = B.device_inputs(synth.to_device_layout(w), prec)
     n = w["n_tracks"]
+    if not graph:
+        flags |= B.TRD_CFG_TIME_KERNEL
     m = B.Matcher(w["params"], prec, block_size=block_size, search_lanes=search_lanes, flags=flags)
     m.reserve(w["n_tracklets"], w["n_groups"], n)
     out = m.alloc_results(n, chi2_layer=False)
@@ -88,6 +117,8 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    if not graph:
+        m.kernel_times()   # drop the warm-up launches
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -101,6 +132,7 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
     st = out["status"].cpu().numpy()
     nm = out["n_match"].cpu().numpy()
     res = dict(wall_ms_per_step=1e3 * wall / steps, bin_ms=t_bin, match_ms=t_match, step_ms=t_step,
+               kernel_ms=(m.kernel_times() if not graph else []),
                n_fallback=int(((st & B.TRK_FP64_FALLBACK) != 0).sum()),
                n_ge2=int((nm >= 2).sum()))
     m.close()
@@ -240,7 +272,7 @@ def main():
     w = synth.load_workload(args.workload)
     P = w["params"]
     n, ntk, ng = w["n_tracks"], w["n_tracklets"], w["n_groups"]
-    n_cells = ng * 540 * P["n_rows"] * P["n_yb"]
+    n_cells = ng * 540 * P["n_rows"] * P["n_yb"] * P["n_db"]
     log(f"{n} tracks, {ntk} tracklets, {n_cells} cells; timing {args.precision}")
     tuned = None
     if args.autotune:
@@ -258,7 +290,11 @@ def main():
     bin_avg = sum(r["bin_ms"]) / len(r["bin_ms"])
     log(f"{ms:.3f} ms/step (bin {bin_avg:.3f} ms, match {match_avg:.3f} ms)")
     ab = match_alg_bytes(n, ntk, n_cells, args.precision)
-    achieved = ab / (match_avg * 1e-3) / 1e9
+    kms = r["kernel_ms"][-args.steps:]
+    kernel_avg = sum(kms) / len(kms) if kms else match_avg
+    achieved = ab / (kernel_avg * 1e-3) / 1e9
+    traffic = profiled_traffic() if (args.workload == "c5_distortion_450k" and args.precision == "fp32"
+                                     and not args.search_lanes > 1 and not args.persistent) else None
     line = {
         "metric": "matched tracks/s (6-layer Kalman)",
         "value": n / (ms * 1e-3),
@@ -283,13 +319,14 @@ def main():
             "step": "bin all tracklets + match all tracks",
         },
         "latency_ms": {"step_p50": pct(r["step_ms"], 50), "step_p99": pct(r["step_ms"], 99),
-                       "bin_avg": bin_avg, "match_avg": match_avg},
+                       "bin_avg": bin_avg, "match_avg": match_avg, "match_kernel_avg": kernel_avg},
         "tracks_ge2_matches_per_s": r["n_ge2"] / (ms * 1e-3),
         "fp64_fallback_tracks": r["n_fallback"],
         "autotune": tuned["table"] if tuned else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_match (trd_match)", "alg_bytes_per_launch": ab},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_match", "alg_bytes_per_launch": ab,
+                     "kernel_ms": kernel_avg},
     }
     if not args.no_fp64 and args.precision != "fp64":
         log("timing the plain FP64 comparator")

@@ -74,6 +74,9 @@ extern "C" {
                                      (group, sector, z, y) of the seed so that neighbouring
                                      lanes read neighbouring cells (results are the same,
                                      bit for bit, and come back in input order) */
+#define TRD_CFG_TIME_KERNEL 16u   /* record HIP events on the launch stream around the
+                                     main match kernel of every trd_match (read them with
+                                     trd_kernel_times) */
 #define TRD_CFG_PERSISTENT 4u     /* one-lane-per-track matching as a persistent grid
                                      (resident workgroups pull blocks of tracks from a
                                      work counter); for large multi-frame batches.
@@ -212,6 +215,14 @@ int trd_copy_binning(trd_ctx *ctx, uint32_t *offsets_out, float *sorted_out, int
 
 /* Device memory currently held by the context, in bytes. */
 int64_t trd_device_bytes(const trd_ctx *ctx);
+
+/* Durations (ms, from HIP events on the launch stream) of the main match
+ * kernel of the last min(calls, 64, max_n) trd_match calls since the
+ * previous read, oldest first, into ms[]; waits for them to finish and
+ * starts a new count.  Returns how many were written (>= 0), or TRD_ESTATE
+ * without TRD_CFG_TIME_KERNEL, TRD_EINVAL, TRD_EDEVICE.  Not for calls
+ * captured into a graph. */
+int trd_kernel_times(trd_ctx *ctx, float *ms, int32_t max_n);
 
 /* Frees everything the context owns.  Waits for its device work. NULL is a no-op. */
 void trd_destroy(trd_ctx *ctx);

@@ -23,10 +23,11 @@ TRD_CFG_FAIL_ALLOC = 1
 TRD_CFG_FORCE_FALLBACK = 2
 TRD_CFG_PERSISTENT = 4
 TRD_CFG_INPUT_ORDER = 8
+TRD_CFG_TIME_KERNEL = 16
 
 # every symbol include/trd.h declares
 EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_get_binning",
-           "trd_copy_binning", "trd_device_bytes", "trd_destroy", "trd_status_string")
+           "trd_copy_binning", "trd_device_bytes", "trd_kernel_times", "trd_destroy", "trd_status_string")
 
 
 class TrdError(RuntimeError):
@@ -92,6 +93,7 @@ def lib():
         L.trd_copy_binning.argtypes = [vp, vp, vp, C.c_int64, vp]
         L.trd_device_bytes.argtypes = [vp]
         L.trd_device_bytes.restype = C.c_int64
+        L.trd_kernel_times.argtypes = [vp, C.POINTER(C.c_float), C.c_int32]
         L.trd_destroy.argtypes = [vp]
         L.trd_destroy.restype = None
         L.trd_status_string.argtypes = [C.c_int]
@@ -173,6 +175,14 @@ def trd_copy_binning(ctx, offsets_ptr, sorted_ptr, max_valid, stream=0):
 
 def trd_device_bytes(ctx) -> int:
     return int(lib().trd_device_bytes(ctx))
+
+
+def trd_kernel_times(ctx, max_n=64):
+    """Durations (ms) of the main match kernel of the recent trd_match calls."""
+    buf = (C.c_float * max(1, max_n))()
+    rc = lib().trd_kernel_times(ctx, buf, int(max_n))
+    _check(min(rc, 0), "trd_kernel_times")
+    return [float(buf[k]) for k in range(rc)]
 
 
 def trd_destroy(ctx):
@@ -282,6 +292,11 @@ class Matcher:
     @property
     def device_bytes(self):
         return trd_device_bytes(self.ctx)
+
+    def kernel_times(self, max_n=64):
+        """Match-kernel durations of the calls since the last read (needs
+        flags=TRD_CFG_TIME_KERNEL)."""
+        return trd_kernel_times(self.ctx, max_n)
 
 
 def device_inputs(dev_layout, precision="fp32", device=0):

@@ -37,6 +37,11 @@ struct trd_ctx {
     uint32_t *d_trank = nullptr, *d_thist = nullptr, *d_thist_off = nullptr, *d_ttiles = nullptr;
     unsigned char *d_rows_in = nullptr, *d_rows_out = nullptr;
 
+    // TRD_CFG_TIME_KERNEL: a ring of event pairs around the main match kernel
+    static constexpr int kEvRing = 64;
+    hipEvent_t ev[kEvRing][2] = {};
+    int64_t ev_count = 0;
+
     int64_t bytes = 0;
     bool loaded = false;
     int64_t n_tkl = 0;
@@ -353,6 +358,13 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out)
     }
     if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->n_cu = 1;
+    if (cfg->flags & TRD_CFG_TIME_KERNEL) {
+        for (int k = 0; k < trd_ctx::kEvRing; k++)
+            if (hipEventCreate(&ctx->ev[k][0]) != hipSuccess || hipEventCreate(&ctx->ev[k][1]) != hipSuccess) {
+                trd_destroy(ctx);
+                return TRD_EDEVICE;
+            }
+    }
     fill_devcfg(ctx->gd, *cfg, (const double *)ctx->d_dx64);
     fill_devcfg(ctx->gf, *cfg, (const float *)ctx->d_dx32);
     if (ctx->cfg.block_size == 0) ctx->cfg.block_size = 256;
@@ -448,6 +460,12 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     io.work_next = ctx->d_small + 2;
     io.work_done = ctx->d_small + 3;
     const hipStream_t s = (hipStream_t)hip_stream;
+    if (ctx->cfg.flags & TRD_CFG_TIME_KERNEL) {
+        const int slot = (int)(ctx->ev_count % trd_ctx::kEvRing);
+        io.ev_begin = ctx->ev[slot][0];
+        io.ev_end = ctx->ev[slot][1];
+        ctx->ev_count++;
+    }
     if (ctx->cfg.n_hyp > 0) {
         launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, s);
         return launch_status();
@@ -495,6 +513,25 @@ int trd_copy_binning(trd_ctx *ctx, uint32_t *offsets_out, float *sorted_out, int
 
 int64_t trd_device_bytes(const trd_ctx *ctx) { return ctx ? ctx->bytes : 0; }
 
+int trd_kernel_times(trd_ctx *ctx, float *ms, int32_t max_n)
+{
+    if (!ctx || (max_n > 0 && !ms) || max_n < 0) return TRD_EINVAL;
+    if (!(ctx->cfg.flags & TRD_CFG_TIME_KERNEL)) return TRD_ESTATE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    int64_t have = ctx->ev_count < trd_ctx::kEvRing ? ctx->ev_count : trd_ctx::kEvRing;
+    if (have > max_n) have = max_n;
+    for (int64_t k = 0; k < have; k++) {
+        const int slot = (int)((ctx->ev_count - have + k) % trd_ctx::kEvRing);
+        if (hipEventSynchronize(ctx->ev[slot][1]) != hipSuccess ||
+            hipEventElapsedTime(&ms[k], ctx->ev[slot][0], ctx->ev[slot][1]) != hipSuccess) {
+            (void)hipGetLastError();
+            return TRD_EDEVICE;
+        }
+    }
+    ctx->ev_count = 0;
+    return (int)have;
+}
+
 void trd_destroy(trd_ctx *ctx)
 {
     if (!ctx) return;
@@ -506,6 +543,9 @@ void trd_destroy(trd_ctx *ctx)
     dev_free(&ctx->d_offsets);
     dev_free(&ctx->d_tiles_cell);
     free_trk(ctx);
+    for (int k = 0; k < trd_ctx::kEvRing; k++)
+        for (int e = 0; e < 2; e++)
+            if (ctx->ev[k][e]) (void)hipEventDestroy(ctx->ev[k][e]);
     delete ctx;
 }
 

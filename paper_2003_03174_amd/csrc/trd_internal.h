@@ -86,6 +86,8 @@ struct MatchIO {
     const void *rows_in;  // [n][kRowIn] of the state type
     void *rows_out;       // [n][kRowOut] of the state type
     int row_out;  // entries per result row: kRowOut, or kRowOutShort without chi2 per layer
+    // host side only: events recorded around the main match kernel (or null)
+    hipEvent_t ev_begin, ev_end;
 };
 
 // Rows of the ordered mode, in units of the state type.

@@ -1312,12 +1312,16 @@ void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &g
                  int n_hyp, hipStream_t s)
 {
     if (io.n <= 0) return;
+    if (io.ev_begin) (void)hipEventRecord(io.ev_begin, s);
     if (precision == 0) {
         launch_beam_t<double, double, false>(gd, io, n_hyp, s);
     } else if (precision == 2) {
         launch_beam_t<float, double, false>(gf, io, n_hyp, s);
     } else {
         launch_beam_t<float, float, true>(gf, io, n_hyp, s);
+    }
+    if (io.ev_end) (void)hipEventRecord(io.ev_end, s);
+    if (precision == 1) {
         switch (n_hyp) {
         case 1: hipLaunchKernelGGL(k_beam_fallback<1>, dim3(64), dim3(256), 0, s, gf, io); break;
         case 2: hipLaunchKernelGGL(k_beam_fallback<2>, dim3(64), dim3(256), 0, s, gf, io); break;
@@ -1459,6 +1463,7 @@ void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &
 {
     if (io.n <= 0) return;
     const unsigned grid = (unsigned)((io.n + block - 1) / block);
+    if (io.ev_begin) (void)hipEventRecord(io.ev_begin, s);
     if (precision == 0) {
         launch_lane<double, double, false>(gd, io, grid, block, persistent, n_cu, s);
     } else if (precision == 2) {
@@ -1471,8 +1476,9 @@ void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &
             launch_lane<float, float, true>(gf, io, grid, block, persistent, n_cu, s);
         else
             launch_coop<float, true>(lanes, gf, io, grid, block, s);
-        hipLaunchKernelGGL(k_match_fallback, dim3(64), dim3(256), 0, s, gf, io);
     }
+    if (io.ev_end) (void)hipEventRecord(io.ev_end, s);
+    if (precision == 1) hipLaunchKernelGGL(k_match_fallback, dim3(64), dim3(256), 0, s, gf, io);
 }
 
 }  // namespace trd

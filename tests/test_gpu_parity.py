@@ -309,3 +309,22 @@ def test_spatial_track_order_is_invisible(prec):
     ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
     rep = pu.compare(ref, a, prec)
     assert rep.ok, rep.summary()
+
+
+def test_kernel_times():
+    """TRD_CFG_TIME_KERNEL: one positive duration per match call, oldest
+    first, and a fresh count after each read; ESTATE without the flag."""
+    w = workload("c1_small_fp64")
+    d = B.device_inputs(synth.to_device_layout(w), "fp32")
+    m = B.Matcher(w["params"], "fp32", flags=B.TRD_CFG_TIME_KERNEL)
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+    for _ in range(3):
+        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    t = m.kernel_times()
+    assert len(t) == 3 and all(v > 0 for v in t)
+    assert m.kernel_times() == []
+    m.close()
+    m = B.Matcher(w["params"], "fp32")
+    with pytest.raises(B.TrdError):
+        m.kernel_times()
+    m.close()
