@@ -637,10 +637,11 @@ __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<T
             }
         }
         // running record counts at the range starts
-        const uint32_t p1 = (e[0] > a[0] ? e[0] - a[0] : 0u);
-        const uint32_t p2 = p1 + (e[1] > a[1] ? e[1] - a[1] : 0u);
-        const uint32_t p3 = p2 + (e[2] > a[2] ? e[2] - a[2] : 0u);
-        const uint32_t tot = p3 + (e[3] > a[3] ? e[3] - a[3] : 0u);
+        uint32_t pre[kBatch + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) pre[u + 1] = pre[u] + (e[u] > a[u] ? e[u] - a[u] : 0u);
+        const uint32_t tot = pre[kBatch];
         for (uint32_t f0 = 0; f0 < tot; f0 += kU) {
             float4 rec[kU];
             int su[kU];
@@ -648,11 +649,15 @@ __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<T
 #pragma unroll
             for (int u = 0; u < kU; u++) {
                 const uint32_t f = f0 + (uint32_t)u;
-                const uint32_t k = f < p1 ? a[0] + f
-                                 : f < p2 ? a[1] + (f - p1)
-                                 : f < p3 ? a[2] + (f - p2)
-                                          : a[3] + (f - p3);
-                su[u] = f < p1 ? st[0] : f < p2 ? st[1] : f < p3 ? st[2] : st[3];
+                // the range holding flat position f: the last one starting at or before it
+                uint32_t k = a[0] + f;
+                su[u] = st[0];
+#pragma unroll
+                for (int q = 1; q < kBatch; q++) {
+                    const bool in = f >= pre[q];
+                    k = in ? a[q] + (f - pre[q]) : k;
+                    su[u] = in ? st[q] : su[u];
+                }
                 dxd[u] = TS(0);
                 if (f < tot) {
                     rec[u] = io.sorted[k];
