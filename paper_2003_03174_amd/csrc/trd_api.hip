@@ -28,7 +28,7 @@ struct trd_ctx {
     uint32_t *d_hist = nullptr, *d_hist_off = nullptr, *d_tiles_tkl = nullptr;
     // cell-side capacity (entries of offsets minus one)
     int64_t cap_cells = 0;
-    uint32_t *d_offsets = nullptr, *d_tiles_cell = nullptr;
+    uint32_t *d_offsets = nullptr;
     // track-side capacity
     int64_t cap_trk = 0;
     int32_t *d_fb = nullptr;
@@ -172,7 +172,7 @@ int64_t tkl_bytes(int64_t n)
     const int64_t m = n > 0 ? n : 1;
     return m * (4 + 4 + 16 + 16) + 8 * hist_len(n) + 4 * scan_block_sums_len(hist_len(n));
 }
-int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1) + 4 * scan_block_sums_len(nc + 1); }
+int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1); }
 // tracks are matched in a spatial order (rows of state in, rows of results
 // out) unless the caller keeps its own order or the launch shape has no use
 // for it (several lanes per road, several hypotheses)
@@ -241,17 +241,11 @@ int ensure_cells(trd_ctx *ctx, int64_t nc)
     const int64_t old = ctx->d_offsets ? cell_bytes(ctx->cap_cells) : 0;
     if (over_budget(ctx, cell_bytes(nc) - old)) return TRD_EBUDGET;
     dev_free(&ctx->d_offsets);
-    dev_free(&ctx->d_tiles_cell);
     ctx->bytes -= old;
     ctx->cap_cells = 0;
     int64_t acc = 0;
-    int rc;
-    if ((rc = dev_alloc(ctx, &ctx->d_offsets, nc + 1, &acc)) ||
-        (rc = dev_alloc(ctx, &ctx->d_tiles_cell, scan_block_sums_len(nc + 1), &acc))) {
-        dev_free(&ctx->d_offsets);
-        dev_free(&ctx->d_tiles_cell);
-        return rc;
-    }
+    const int rc = dev_alloc(ctx, &ctx->d_offsets, nc + 1, &acc);
+    if (rc) return rc;
     ctx->bytes += cell_bytes(nc);
     ctx->cap_cells = nc;
     return TRD_OK;
@@ -412,7 +406,6 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
     buf.hist_off = ctx->d_hist_off;
     buf.tiles_tkl = ctx->d_tiles_tkl;
     buf.offsets = ctx->d_offsets;
-    buf.tiles_cell = ctx->d_tiles_cell;
     launch_bin(t->y, t->z, t->dy, t->det_row, t->group, n, b, buf, s);
     if ((rc = launch_status())) return rc;
     ctx->loaded = true;
@@ -541,7 +534,6 @@ void trd_destroy(trd_ctx *ctx)
     dev_free(&ctx->d_small);
     free_tkl(ctx);
     dev_free(&ctx->d_offsets);
-    dev_free(&ctx->d_tiles_cell);
     free_trk(ctx);
     for (int k = 0; k < trd_ctx::kEvRing; k++)
         for (int e = 0; e < 2; e++)

@@ -224,14 +224,34 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// first sorted position of each key: offsets[key[p]] = p at run starts
+// Cell offsets from the sorted keys in one pass: offsets[c] is the first
+// sorted position whose key is >= c, for c in [0, n_cells].  Position p
+// (0 <= p <= n, with p = n standing for the end) owns the cells
+// (key[p-1], key[p]] and writes p into each, so every cell is written once.
+// Short runs are written by their lane, long runs (empty stretches of the
+// detector) by the whole wavefront in turn.
+constexpr int64_t kShortRun = 16;
 __global__ void __launch_bounds__(kBlock)
-    k_run_starts(const uint32_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ offsets)
+    k_offsets(const uint32_t *__restrict__ keys, int64_t n, uint32_t n_cells, uint32_t *__restrict__ offsets)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) offsets[k] = (uint32_t)p;
+    int64_t lo = 1, hi = 0;
+    if (p <= n) {
+        lo = p == 0 ? 0 : (int64_t)keys[p - 1] + 1;
+        hi = p == n ? (int64_t)n_cells : (int64_t)keys[p];
+    }
+    const bool is_long = hi - lo + 1 > kShortRun;
+    if (!is_long)
+        for (int64_t c = lo; c <= hi; c++) offsets[c] = (uint32_t)p;
+    uint64_t m = __ballot(is_long);
+    const int lane = threadIdx.x & 63;
+    while (m) {
+        const int src = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int64_t l0 = __shfl(lo, src, 64), h0 = __shfl(hi, src, 64);
+        const uint32_t v = (uint32_t)__shfl((int)p, src, 64);
+        for (int64_t c = l0 + lane; c <= h0; c += 64) offsets[c] = v;
+    }
 }
 
 // load the kScanItems values owned by this thread (pad past the end)
@@ -321,98 +341,6 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---- suffix minimum (offsets of empty cells = start of the next run) ----
 
-__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_down(v, d, 64);
-        if (lane + d < 64) v = t < v ? t : v;
-    }
-    return v;
-}
-
-// inclusive suffix minimum over the workgroup, given each thread's value
-__device__ __forceinline__ uint32_t block_suffix_min(uint32_t v)
-{
-    __shared__ uint32_t wmin[kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t s = wave_suffix_min(v);
-    if (lane == 0) wmin[wid] = s;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; w++)
-        if (w > wid) s = wmin[w] < s ? wmin[w] : s;
-    __syncthreads();
-    return s;
-}
-
-// value held by thread tid + 1 of the workgroup (all-ones for the last one)
-__device__ __forceinline__ uint32_t block_next(uint32_t v)
-{
-    __shared__ uint32_t firsts[kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t nx = __shfl_down(v, 1, 64);
-    if (lane == 0) firsts[wid] = v;
-    __syncthreads();
-    if (lane == 63) nx = wid + 1 < kBlock / 64 ? firsts[wid + 1] : 0xffffffffu;
-    __syncthreads();
-    return nx;
-}
-
-__global__ void __launch_bounds__(kBlock)
-    k_min_reduce(const uint32_t *__restrict__ in, int64_t n, uint32_t *__restrict__ tile_min)
-{
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    load_items(in, n, base, 0xffffffffu, v);
-    uint32_t m = 0xffffffffu;
-#pragma unroll
-    for (int j = 0; j < kScanItems; j++) m = v[j] < m ? v[j] : m;
-    m = block_suffix_min(m);
-    if (threadIdx.x == 0) tile_min[blockIdx.x] = m;
-}
-
-// one workgroup: each tile minimum becomes the minimum over the later tiles
-__global__ void __launch_bounds__(kBlock) k_min_top(uint32_t *__restrict__ mins, int64_t nb)
-{
-    __shared__ uint32_t head;
-    uint32_t carry = 0xffffffffu;
-    const int64_t nchunks = (nb + kBlock - 1) / kBlock;
-    for (int64_t c = nchunks - 1; c >= 0; c--) {
-        const int64_t i = c * kBlock + threadIdx.x;
-        const uint32_t v = i < nb ? mins[i] : 0xffffffffu;
-        const uint32_t incl = block_suffix_min(v);
-        const uint32_t nx = block_next(incl);
-        if (i < nb) mins[i] = nx < carry ? nx : carry;
-        if (threadIdx.x == 0) head = incl;
-        __syncthreads();
-        carry = head < carry ? head : carry;
-        __syncthreads();
-    }
-}
-
-// in place: each value becomes the minimum of itself and everything after it
-__global__ void __launch_bounds__(kBlock)
-    k_min_down(uint32_t *__restrict__ a, int64_t n, const uint32_t *__restrict__ tile_after)
-{
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    load_items(a, n, base, 0xffffffffu, v);
-    uint32_t m = 0xffffffffu;
-#pragma unroll
-    for (int j = 0; j < kScanItems; j++) m = v[j] < m ? v[j] : m;
-    const uint32_t nx = block_next(block_suffix_min(m));  // later threads of this tile
-    const uint32_t t = tile_after[blockIdx.x];            // later tiles
-    uint32_t run = nx < t ? nx : t;
-#pragma unroll
-    for (int j = kScanItems - 1; j >= 0; j--) {
-        run = v[j] < run ? v[j] : run;
-        v[j] = run;
-    }
-    store_items(a, n, base, v);
-}
-
 inline unsigned grid_for(int64_t n, int block)
 {
     int64_t g = (n + block - 1) / block;
@@ -443,16 +371,6 @@ static void launch_excl_scan(const uint32_t *in, int64_t n, uint32_t *tiles, uin
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tiles, out);
 }
 
-// in-place inclusive suffix minimum of n values
-static void launch_suffix_min(uint32_t *a, int64_t n, uint32_t *tiles, hipStream_t s)
-{
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (nb == 0) return;
-    hipLaunchKernelGGL(k_min_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, a, n, tiles);
-    hipLaunchKernelGGL(k_min_top, dim3(1), dim3(kBlock), 0, s, tiles, nb);
-    hipLaunchKernelGGL(k_min_down, dim3((unsigned)nb), dim3(kBlock), 0, s, a, n, tiles);
-}
-
 // One radix pass from src into (keys_out, recs_out).
 template <typename Src>
 static void radix_pass(const Src &src, int64_t n, int shift, uint32_t *hist, uint32_t *hist_off,
@@ -477,9 +395,7 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
                 const int32_t *grp, int64_t n, const BinCfg &b, BinBuffers &buf, hipStream_t s)
 {
     const int64_t nc = (int64_t)b.n_cells;
-    // offsets: n for the end sentinel, "none" elsewhere until run starts fill in
-    launch_fill_u32(buf.offsets, 0xffffffffu, nc, s);
-    launch_fill_u32(buf.offsets + nc, (uint32_t)n, 1, s);
+    const uint32_t *sorted_keys = nullptr;
     if (n > 0) {
         const int passes = radix_passes((uint64_t)nc);
         // ping-pong so that the last pass lands in buf.sorted
@@ -495,11 +411,10 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
             src = PassSrc<float4>{kdst[out], rdst[out]};
             out ^= 1;
         }
-        hipLaunchKernelGGL(k_run_starts, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, src.keys, n,
-                           buf.offsets);
-        buf.sorted_keys = src.keys;
+        sorted_keys = src.keys;
     }
-    launch_suffix_min(buf.offsets, nc + 1, buf.tiles_cell, s);
+    hipLaunchKernelGGL(k_offsets, dim3(grid_for(n + 1, kBlock)), dim3(kBlock), 0, s, sorted_keys, n,
+                       (uint32_t)nc, buf.offsets);
 }
 
 template <typename TS>

@@ -50,8 +50,6 @@ struct BinBuffers {
     uint32_t *hist, *hist_off;  // [radix_blocks(cap) * 256] digit histograms
     uint32_t *tiles_tkl;        // [scan_block_sums_len(radix_blocks(cap) * 256)]
     uint32_t *offsets;          // [n_cells + 1]
-    uint32_t *tiles_cell;       // [scan_block_sums_len(n_cells + 1)]
-    const uint32_t *sorted_keys;  // set by launch_bin: keys in sorted order
 };
 
 // launchers (stream-ordered, no synchronisation)
