@@ -86,6 +86,7 @@ struct TklSrc {
     const uint32_t *det_row;
     const int32_t *grp;
     BinCfg b;
+    const uint32_t *cached;  // keys written by the histogram pass (null there)
     using Rec = float4;
     __device__ __forceinline__ uint32_t key(int64_t e) const
     {
@@ -94,7 +95,7 @@ struct TklSrc {
     __device__ __forceinline__ void load(int64_t e, uint32_t &k, float4 &rec) const
     {
         const float ye = y[e], ze = z[e], dye = dy[e];
-        k = cell_key(ye, ze, dye, det_row[e], grp ? grp[e] : 0, b);
+        k = cached ? cached[e] : cell_key(ye, ze, dye, det_row[e], grp ? grp[e] : 0, b);
         rec = make_float4(ye, dye, ze, __int_as_float((int)e));
     }
 };
@@ -134,7 +135,7 @@ struct PassSrc {
 // digit histogram of one tile, stored digit-major: hist[d * n_blocks + block]
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
-    k_radix_hist(Src src, int64_t n, int shift, uint32_t *__restrict__ hist)
+    k_radix_hist(Src src, int64_t n, int shift, uint32_t *__restrict__ hist, uint32_t *__restrict__ key_out)
 {
     __shared__ uint32_t h[kBins];
     h[threadIdx.x] = 0;
@@ -143,7 +144,11 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
         const int64_t e = base + j * kBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(src.key(e) >> shift) & (kBins - 1)], 1u);
+        if (e < n) {
+            const uint32_t k = src.key(e);
+            if (key_out) key_out[e] = k;
+            atomicAdd(&h[(k >> shift) & (kBins - 1)], 1u);
+        }
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -178,12 +183,22 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    // all of this thread's elements in flight at once
+    uint32_t kv[kSub];
+    Rec rv[kSub];
+#pragma unroll
+    for (int j = 0; j < kSub; j++) {
+        const int64_t e = base + j * kBlock + tid;
+        kv[j] = 0;
+        rv[j] = Rec{};
+        if (e < n) src.load(e, kv[j], rv[j]);
+    }
+#pragma unroll
     for (int j = 0; j < kSub; j++) {
         const int64_t e = base + j * kBlock + tid;
         const bool valid = e < n;
-        uint32_t key = 0;
-        Rec rec{};
-        if (valid) src.load(e, key, rec);
+        const uint32_t key = kv[j];
+        const Rec rec = rv[j];
         const uint32_t d = (key >> shift) & (kBins - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -378,10 +393,26 @@ static void radix_pass(const Src &src, int64_t n, int shift, uint32_t *hist, uin
                        uint32_t *rank_out = nullptr)
 {
     const int64_t nblk = radix_blocks(n);
-    hipLaunchKernelGGL(k_radix_hist<Src>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift, hist);
+    hipLaunchKernelGGL(k_radix_hist<Src>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift, hist,
+                       (uint32_t *)nullptr);
     launch_excl_scan(hist, nblk * kBins, tiles, hist_off, s);
     hipLaunchKernelGGL(k_radix_scatter<Src>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift, hist,
                        hist_off, keys_out, recs_out, rank_out);
+}
+
+// First pass of the tracklet sort: the histogram pass computes the keys once
+// and leaves them in key_cache for the scatter.
+static void radix_pass_tkl(TklSrc src, int64_t n, uint32_t *key_cache, uint32_t *hist, uint32_t *hist_off,
+                           uint32_t *tiles, uint32_t *keys_out, float4 *recs_out, hipStream_t s)
+{
+    const int64_t nblk = radix_blocks(n);
+    src.cached = nullptr;
+    hipLaunchKernelGGL(k_radix_hist<TklSrc>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, hist,
+                       key_cache);
+    launch_excl_scan(hist, nblk * kBins, tiles, hist_off, s);
+    src.cached = key_cache;
+    hipLaunchKernelGGL(k_radix_scatter<TklSrc>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, hist,
+                       hist_off, keys_out, recs_out, (uint32_t *)nullptr);
 }
 
 static int radix_passes(uint64_t max_key)
@@ -402,8 +433,9 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
         uint32_t *kdst[2] = {buf.keys_a, buf.keys_b};
         float4 *rdst[2] = {buf.sorted, buf.recs_tmp};
         int out = (passes % 2 == 1) ? 0 : 1;
-        radix_pass(TklSrc{y, z, dy, det_row, grp, b}, n, 0, buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
-                   rdst[out], s);
+        // the other key buffer is free during the first pass
+        radix_pass_tkl(TklSrc{y, z, dy, det_row, grp, b, nullptr}, n, kdst[out ^ 1], buf.hist, buf.hist_off,
+                       buf.tiles_tkl, kdst[out], rdst[out], s);
         PassSrc<float4> src{kdst[out], rdst[out]};
         out ^= 1;
         for (int p = 1; p < passes; p++) {
