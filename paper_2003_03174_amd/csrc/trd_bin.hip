@@ -319,32 +319,23 @@ __global__ void __launch_bounds__(kBlock)
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// one workgroup: exclusive scan of the per-tile sums in place
-__global__ void __launch_bounds__(kBlock) k_scan_top(uint32_t *__restrict__ sums, int64_t nb)
-{
-    uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
-        const int64_t i = b0 + threadIdx.x;
-        const uint32_t v = i < nb ? sums[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, &tot);
-        if (i < nb) sums[i] = carry + ex;
-        carry += tot;
-    }
-}
-
 __global__ void __launch_bounds__(kBlock)
-    k_scan_down(const uint32_t *__restrict__ in, int64_t n, const uint32_t *__restrict__ tile_off,
+    k_scan_down(const uint32_t *__restrict__ in, int64_t n, const uint32_t *__restrict__ tile_sums,
                 uint32_t *__restrict__ out)
 {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     load_items(in, n, base, 0u, v);
+    // this tile's offset: the sums of the earlier tiles (a few hundred at most)
+    uint32_t part = 0;
+    for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += kBlock) part += tile_sums[t];
+    uint32_t tile_off;
+    (void)block_excl_scan(part, &tile_off);
     uint32_t s = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) s += v[j];
     uint32_t tot;
-    uint32_t run = block_excl_scan(s, &tot) + tile_off[blockIdx.x];
+    uint32_t run = block_excl_scan(s, &tot) + tile_off;
     uint32_t o[kScanItems];
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
@@ -382,7 +373,6 @@ static void launch_excl_scan(const uint32_t *in, int64_t n, uint32_t *tiles, uin
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) return;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tiles, nb);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tiles, out);
 }
 
