@@ -43,22 +43,28 @@ __device__ __forceinline__ double as_row(int v, double) { return (double)v; }
 __device__ __forceinline__ int int_of(float v) { return __float_as_int(v); }
 __device__ __forceinline__ int int_of(double v) { return (int)v; }
 
-template <typename T> __device__ __forceinline__ T sinc_(T u) { return u == T(0) ? T(1) : sin(u) / u; }
+// Division: the float paths take one hardware reciprocal (1 ulp) and a
+// multiply instead of the IEEE division sequence (the float state is held to
+// 1e-5 anyway); the double paths divide exactly.
+__device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double div_(double a, double b) { return a / b; }
+
+template <typename T> __device__ __forceinline__ T sinc_(T u) { return u == T(0) ? T(1) : div_(T(sin(u)), u); }
 
 // (sin d - d) / d^2; Taylor series below |d| = 0.5 where the direct form cancels
 template <typename T> __device__ __forceinline__ T gfun(T d)
 {
     if (fabs(d) < T(0.5)) {
         const T d2 = d * d;
-        T term = -d / T(6), sum = T(0);
+        T term = div_(-d, T(6)), sum = T(0);
 #pragma unroll
         for (int k = 1; k <= 8; k++) {
             sum += term;
-            term *= -d2 / (T(2 * k + 2) * T(2 * k + 3));
+            term *= div_(-d2, T(2 * k + 2) * T(2 * k + 3));
         }
         return sum;
     }
-    return (sin(d) - d) / (d * d);
+    return div_(T(sin(d)) - d, d * d);
 }
 
 // Helix step in the sector frame from T.x to x2, with the exact Jacobian
@@ -76,20 +82,20 @@ __device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS
     const TS f1 = sqrt(TS(1) - s1 * s1);
     const TS f2 = sqrt(TS(1) - s2 * s2);
     const TS ff = f1 + f2;
-    const TS dy = dx * (s1 + s2) / ff;
+    const TS dy = div_(dx * (s1 + s2), ff);
     const TS chord = sqrt(dx * dx + dy * dy);
     const TS h = TS(0.5) * fabs(cu) * chord;
-    const TS aoh = h > TS(0) ? asin(h) / h : TS(1);
+    const TS aoh = h > TS(0) ? div_(TS(asin(h)), h) : TS(1);
     const TS arc = (dx >= TS(0) ? chord : -chord) * aoh;
     const TS delta = cu * arc;
     const TS t = T.t;
 
     // Jacobian entries (identity elsewhere)
     const TC f12 = TC(f1) * TC(f2);
-    const TC a = TC(arc) * sinc_(TC(delta)) / f12;                        // dy/ds
-    const TC b = TC(k) * sq(TC(dx)) / TC(ff) *
-                 (TC(1) + TC(s2) * TC(s1 + s2) / (TC(f2) * TC(ff)));        // dy/dc
-    const TC d = TC(t) * TC(dy) / f12;                                      // dz/ds
+    const TC a = div_(TC(arc) * sinc_(TC(delta)), f12);                   // dy/ds
+    const TC b = div_(TC(k) * sq(TC(dx)), TC(ff)) *
+                 (TC(1) + div_(TC(s2) * TC(s1 + s2), TC(f2) * TC(ff)));     // dy/dc
+    const TC d = div_(TC(t) * TC(dy), f12);                                 // dz/ds
     const TC e = TC(arc);                                                   // dz/dt
     const TC sh = sinc_(TC(0.5) * TC(delta));
     const TC f = TC(k) * TC(t) * sq(TC(arc)) *
@@ -142,10 +148,10 @@ __device__ __forceinline__ bool rotate(Trk<TS, TC> &T, bool up, const DevCfg<TS>
     if (!(f1 > TS(0))) return false;
     const TS x1 = T.x * ca + T.y * sa;
     const TS y1 = -T.x * sa + T.y * ca;
-    const TC A = TC(f) / TC(f1);
-    const TC B = -TC(sa) * TC(T.t) / TC(f1);
+    const TC A = div_(TC(f), TC(f1));
+    const TC B = div_(-TC(sa) * TC(T.t), TC(f1));
     const TC Cc = -TC(g.k_curv) * TC(T.c) * TC(sa);
-    const TC Dd = TC(f1) / TC(f);
+    const TC Dd = div_(TC(f1), TC(f));
     T.y = y1;
     T.s = s1;
     T.x = x1;
@@ -176,10 +182,10 @@ __device__ __forceinline__ void add_ms(Trk<TS, TC> &T, const DevCfg<TS> &g)
     if (c == TC(0) || !(g.x_over_x0 > TS(0))) return;
     const TC f = sqrt(TC(1) - s * s);
     const TC tt = TC(1) + t * t;
-    const TC pp = sqrt(tt) / fabs(c);
-    const TC beta = pp / sqrt(pp * pp + TC(g.mass2));
-    const TC xi = TC(g.x_over_x0) * sqrt(tt) / f;
-    const TC th0 = TC(0.0136) / (beta * pp) * sqrt(xi) * (TC(1) + TC(0.038) * log(xi));
+    const TC pp = div_(TC(sqrt(tt)), TC(fabs(c)));
+    const TC beta = div_(pp, TC(sqrt(pp * pp + TC(g.mass2))));
+    const TC xi = div_(TC(g.x_over_x0) * TC(sqrt(tt)), f);
+    const TC th0 = div_(TC(0.0136), beta * pp) * sqrt(xi) * (TC(1) + TC(0.038) * log(xi));
     const TC th2 = th0 * th0;
     T.C[SS] += th2 * f * f * tt;
     T.C[TT] += th2 * tt * tt;
@@ -211,7 +217,7 @@ template <typename TC> __device__ __forceinline__ bool ldl_pd(const TC *C)
             TC w = cget(C, i, j);
 #pragma unroll
             for (int k2 = 0; k2 < j; k2++) w -= L[i][k2] * L[j][k2] * dd[k2];
-            L[i][j] = w / v;
+            L[i][j] = w / v;  // IEEE division: the check's decisions are those of plain float
         }
     }
     return true;
@@ -234,7 +240,7 @@ __device__ __forceinline__ bool kalman_update(Trk<TS, TC> &T, TS ry, TS rz, TS t
     const TC S01 = H1[0] + tc * H1[1];
     const TC S11 = H1[1] + vz;
     const TC det = S00 * S11 - S01 * S01;
-    const TC i00 = S11 / det, i01 = -S01 / det, i11 = S00 / det;
+    const TC i00 = div_(S11, det), i01 = div_(-S01, det), i11 = div_(S00, det);
     TC K0[5], K1[5];
 #pragma unroll
     for (int i = 0; i < 5; i++) {
@@ -432,8 +438,8 @@ __device__ __forceinline__ bool open_road(const Trk<TS, TC> &T, int l, int grp, 
     R.y = T.y;
     R.z = T.z;
     R.tau = tau;
-    R.tphi = T.s / f;
-    R.tz = T.t / f;
+    R.tphi = div_(T.s, f);
+    R.tz = div_(T.t, f);
     const TS sy = poly2(g.sigma_y, T.s);
     const TC vy = TC(sy) * TC(sy);
     const TC Syy = T.C[YY] + TC(2) * TC(tau) * T.C[YZ] + TC(tau) * TC(tau) * T.C[ZZ] + vy;
@@ -446,16 +452,16 @@ __device__ __forceinline__ bool open_road(const Trk<TS, TC> &T, int l, int grp, 
         status |= kNotPD;
         return false;
     }
-    R.si00 = TS(Szz / det);
-    R.si01 = TS(-Syz / det);
-    R.si11 = TS(Syy / det);
+    R.si00 = TS(div_(Szz, det));
+    R.si01 = TS(div_(-Syz, det));
+    R.si11 = TS(div_(Syy, det));
     R.Ry = g.n_sigma_road * TS(sqrt(Syy));
     R.Rz = g.n_sigma_road * TS(sqrt(Szz));
     R.dytrk = g.drift_len * (R.tphi - g.tan_psi);
     const TS sdy = poly2(g.sigma_dy, T.s);
     const TS f3 = f * f * f;
     R.gdy = g.n_sigma_dy *
-            TS(sqrt(TC(sdy) * TC(sdy) + TC(g.drift_len) * TC(g.drift_len) * T.C[SS] / (TC(f3) * TC(f3))));
+            TS(sqrt(TC(sdy) * TC(sdy) + div_(TC(g.drift_len) * TC(g.drift_len) * T.C[SS], TC(f3) * TC(f3))));
     const TS mz = g.dx_max * fabs(R.tz);
     if (T.z + R.Rz + mz < g.z_min || T.z - R.Rz - mz > g.z_max) {
         status |= kOutOfZ;
