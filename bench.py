@@ -167,10 +167,20 @@ def cpu_baseline(w, budget_s=12.0):
     t_call = time.perf_counter() - t0
     per_trk = max(t_call - t_bin, 1e-9) / sample.size
     est = t_bin + per_trk * n
+    # one thread: the binning and a smaller sample, same extrapolation
+    s1 = np.arange(0, n, max(1, n // 20000))
+    t0 = time.perf_counter()
+    O.match(P, w, threads=1, track_slice=s1)
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.bin_tracklets(P, w)
+    t_bin1 = time.perf_counter() - t0   # the binning is single-threaded in the oracle
+    est1 = t_bin1 + max(t_one - t_bin1, 1e-9) / s1.size * n
     return dict(value=n / est, unit="tracks/s", cores=int(O.lib().oracle_max_threads()), kind="oracle",
+                value_1_thread=n / est1,
                 sample=(f"binning of all {w['n_tracklets']} tracklets ({t_bin:.2f} s) + matching of "
                         f"{sample.size} of {n} tracks (every {max(1, n // ns)}th, {t_call - t_bin:.2f} s), "
-                        f"extrapolated to the whole batch"))
+                        f"extrapolated to the whole batch; 1 thread: {s1.size} tracks"))
 
 
 def serve_bench(args):
@@ -236,6 +246,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
     ap.add_argument("--graph", action="store_true", help="replay bin + match as one captured graph")
+    ap.add_argument("--n-hyp", type=int, default=0,
+                    help="hypotheses kept per layer (0: the single best candidate)")
+    ap.add_argument("--chi2-penalty", type=float, default=None,
+                    help="cost of a layer without a tracklet when --n-hyp > 0 (default chi2_max)")
     ap.add_argument("--persistent", action="store_true",
                     help="one-lane-per-track match as a persistent grid")
     ap.add_argument("--autotune", action="store_true", help="pick block size and lanes per track first")
@@ -270,6 +284,11 @@ def main():
         del src, dst
     log(f"generating {args.workload}")
     w = synth.load_workload(args.workload)
+    if args.n_hyp:
+        w = dict(w)
+        w["params"] = dict(w["params"], n_hyp=args.n_hyp,
+                           chi2_penalty=(args.chi2_penalty if args.chi2_penalty is not None
+                                         else w["params"]["chi2_max"]))
     P = w["params"]
     n, ntk, ng = w["n_tracks"], w["n_tracklets"], w["n_groups"]
     n_cells = ng * 540 * P["n_rows"] * P["n_yb"] * P["n_db"]
@@ -294,7 +313,8 @@ def main():
     kernel_avg = sum(kms) / len(kms) if kms else match_avg
     achieved = ab / (kernel_avg * 1e-3) / 1e9
     traffic = profiled_traffic() if (args.workload == "c5_distortion_450k" and args.precision == "fp32"
-                                     and not args.search_lanes > 1 and not args.persistent) else None
+                                     and not args.search_lanes > 1 and not args.persistent
+                                     and not args.n_hyp) else None
     line = {
         "metric": "matched tracks/s (6-layer Kalman)",
         "value": n / (ms * 1e-3),
@@ -316,6 +336,8 @@ def main():
             "block_size": args.block_size or 256,
             "search_lanes": args.search_lanes or 1,
             "persistent": bool(args.persistent),
+            "n_hyp": args.n_hyp,
+            "chi2_penalty": P.get("chi2_penalty") if args.n_hyp else None,
             "step": "bin all tracklets + match all tracks",
         },
         "latency_ms": {"step_p50": pct(r["step_ms"], 50), "step_p99": pct(r["step_ms"], 99),
@@ -325,7 +347,7 @@ def main():
         "autotune": tuned["table"] if tuned else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_match", "alg_bytes_per_launch": ab,
+                     "kernel": "k_match_beam" if args.n_hyp else "k_match", "alg_bytes_per_launch": ab,
                      "kernel_ms": kernel_avg},
     }
     if not args.no_fp64 and args.precision != "fp64":
