@@ -36,7 +36,12 @@ class OCfg(C.Structure):
         ("m_chi2", C.c_double), ("m_snp", C.c_double),
         ("n_rows", C.c_int32), ("n_yb", C.c_int32), ("n_db", C.c_int32),
         ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
+        ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32), ("pad_", C.c_int32),
     ]
+
+# TRD-only refit defaults: starting covariance diag (cm^2, cm^2, -, -, (c/GeV)^2)
+REFIT_COV = (1.0, 100.0, 1e-2, 1e-2, 1.0)
+REFIT_MIN = 4
 
 
 def build(force=False):
@@ -105,6 +110,9 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
     c.n_rows, c.n_yb = P["n_rows"], P["n_yb"]
     c.n_hyp = int(P.get("n_hyp", 0))
     c.chi2_penalty = float(P.get("chi2_penalty", P["chi2_max"]))
+    for k in range(5):
+        c.refit_cov[k] = float(P.get("refit_cov", REFIT_COV)[k])
+    c.refit_min = int(P.get("refit_min", REFIT_MIN))
     return c
 
 
@@ -178,6 +186,29 @@ def match(params, w, *, mode="binned", threads=0, layers=False, margins=None, tr
         _ptr(o["n_match"], ip), _ptr(o["status"], up), _ptr(o["flags"], up),
         _ptr(o["flag_layer"], ip), _ptr(o["n_cand"], C.c_int64),
         _ptr(o.get("lp"), dp), _ptr(o.get("lc"), dp), _ptr(o.get("lx"), dp), _ptr(o.get("lsec"), ip))
+    assert rc == 0, rc
+    return o
+
+
+def refit(params, tracks, idx, w, threads=0):
+    """TRD-only refit of matched tracks.  tracks: dict with p [5][n], x, sector
+    (e.g. the output of match()); idx [6][n] the matched tracklet indices;
+    w: the workload's tracklets.  Returns p, cov, x, sector, chi2, n_used, status."""
+    L = lib()
+    cfg = make_cfg(params)
+    tp, tx = _f64(tracks["p"]), _f64(tracks["x"])
+    ts = np.ascontiguousarray(tracks["sector"], dtype=np.int32)
+    ix = np.ascontiguousarray(idx, dtype=np.int32)
+    n = int(tx.size)
+    y, z = _f64(w["tkl_y"]), _f64(w["tkl_z"])
+    dr = np.ascontiguousarray(w["tkl_det_row"], dtype=np.uint32)
+    o = dict(p=np.zeros((5, n)), cov=np.zeros((15, n)), x=np.zeros(n), sector=np.zeros(n, np.int32),
+             chi2=np.zeros(n), n_used=np.zeros(n, np.int32), status=np.zeros(n, np.uint32))
+    dp, ip_, up = C.c_double, C.c_int32, C.c_uint32
+    rc = L.oracle_refit(C.byref(cfg), n, _ptr(tp, dp), _ptr(tx, dp), _ptr(ts, ip_), _ptr(ix, ip_),
+                        int(y.size), _ptr(y, dp), _ptr(z, dp), _ptr(dr, up), int(threads),
+                        _ptr(o["p"], dp), _ptr(o["cov"], dp), _ptr(o["x"], dp), _ptr(o["sector"], ip_),
+                        _ptr(o["chi2"], dp), _ptr(o["n_used"], ip_), _ptr(o["status"], up))
     assert rc == 0, rc
     return o
 

@@ -59,6 +59,8 @@
 #define ST_ROT_FAIL 2u
 #define ST_OUT_OF_Z 4u
 #define ST_BAD_INPUT 32u
+#define ST_REFIT_FEW 64u   /* refit: fewer tracklets than refit_min, copied */
+#define ST_REFIT_SKIP 128u /* refit: a tracklet more than one sector away was skipped */
 /* decision-margin flags */
 #define FL_P1 1u /* winner near one of its gates */
 #define FL_P2 2u /* a loser fails exactly one gate by a margin and would win */
@@ -80,6 +82,8 @@ typedef struct {
     int32_t n_rows, n_yb, n_db;
     int32_t n_hyp;              /* 0: single best candidate; >= 1: hypotheses kept per layer */
     double chi2_penalty;        /* cost of a layer without a tracklet (hypothesis mode) */
+    double refit_cov[5];        /* TRD-only refit: starting covariance (diagonal) */
+    int32_t refit_min, pad_;    /* TRD-only refit: fewest tracklets refitted */
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -984,6 +988,123 @@ int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *t
     }
     free(perm);
     free(offsets);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* TRD-only refit (Sect. 2, step 3: refits from the outer detectors with   */
+/* the TPC information ignored)                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Readings where the paper is silent:
+ *   - the refit starts from the matched track's final state with the
+ *     covariance replaced by diag(refit_cov), which drops what the TPC
+ *     contributed to it;
+ *   - it runs inward over layers 5..0: propagate to the layer plane (sector
+ *     hops as in the matching); with a tracklet at that layer, turn into the
+ *     tracklet's sector if it is a neighbour (else skip it, REFIT_SKIP), step
+ *     to x_l + dx and update; then add the layer's scattering, except at
+ *     layer 0;
+ *   - the result is the state after layer 0; chi2 is the sum of the
+ *     predicted chi2 of the updates;
+ *   - fewer than refit_min tracklets: the input state is copied with the
+ *     starting covariance and REFIT_FEW. */
+static void refit_one(const ocfg *g, int64_t i, int64_t n, const double *ip, const double *ix,
+                      const int32_t *isec, const int32_t *idx, int64_t n_tkl, const double *ky,
+                      const double *kz, const uint32_t *kdr, double *op, double *oc, double *ox,
+                      int32_t *osec, double *ochi2, int32_t *onused, uint32_t *ostatus)
+{
+    const double tan10 = tan(M_PI / NSEC), dphi = 2.0 * M_PI / NSEC;
+    double p[5], C[5][5], x = ix[i], chi2 = 0.0;
+    int sec = isec[i], nused = 0, nm = 0;
+    unsigned status = 0;
+    memset(C, 0, sizeof(C));
+    for (int k = 0; k < 5; k++) {
+        p[k] = ip[k * n + i];
+        C[k][k] = g->refit_cov[k];
+    }
+    for (int l = 0; l < NLAY; l++) {
+        int32_t j = idx[l * n + i];
+        if (j >= 0 && j < n_tkl) nm++;
+    }
+    int bad = !(isfinite(x) && sec >= 0 && sec < NSEC);
+    for (int k = 0; k < 5; k++) bad |= !isfinite(p[k]);
+    if (!bad) bad = !(fabs(p[2]) < g->snp_max);
+    if (bad) {
+        status = ST_BAD_INPUT;
+    } else if (nm < g->refit_min) {
+        status = ST_REFIT_FEW;
+    } else {
+        const double vz = g->pad_len * g->pad_len / 12.0;
+        for (int l = NLAY - 1; l >= 0 && !(status & (ST_STOP_SNP | ST_ROT_FAIL)); l--) {
+            const double xl = g->x_layer[l];
+            if (!propagate(p, C, &x, xl, g, NULL, NULL)) { status |= ST_STOP_SNP; break; }
+            for (int nrot = 0;; nrot++) {
+                if (fabs(p[0]) <= xl * tan10) break;
+                if (nrot == 2) { status |= ST_ROT_FAIL; break; }
+                int up = p[0] > 0;
+                if (!rotate(p, C, &x, up ? dphi : -dphi, g, NULL)) { status |= ST_ROT_FAIL; break; }
+                sec = (sec + (up ? 1 : NSEC - 1)) % NSEC;
+                if (!propagate(p, C, &x, xl, g, NULL, NULL)) { status |= ST_STOP_SNP; break; }
+            }
+            if (status & (ST_STOP_SNP | ST_ROT_FAIL)) break;
+            int32_t j = idx[l * n + i];
+            if (j >= 0 && j < n_tkl) {
+                const int det = (int)(kdr[j] >> 5), st = det / (NSTK * NLAY);
+                int ok = 1;
+                if (st != sec) {
+                    int d = (st - sec + NSEC) % NSEC;
+                    if (d == 1 || d == NSEC - 1) {
+                        if (!rotate(p, C, &x, d == 1 ? dphi : -dphi, g, NULL)) { status |= ST_ROT_FAIL; break; }
+                        sec = st;
+                        if (!propagate(p, C, &x, xl, g, NULL, NULL)) { status |= ST_STOP_SNP; break; }
+                    } else {
+                        status |= ST_REFIT_SKIP;
+                        ok = 0;
+                    }
+                }
+                if (ok) {
+                    const double dxj = g->dx_chamber[det];
+                    if (dxj != 0.0 && !propagate(p, C, &x, xl + dxj, g, NULL, NULL)) { status |= ST_STOP_SNP; break; }
+                    const double tau = g->tilt[l];
+                    const double ry = ky[j] - (p[0] + tau * (p[1] - kz[j]));
+                    const double rz = kz[j] - p[1];
+                    const double sy = poly2(g->sigma_y, p[2]);
+                    const double Syy = C[0][0] + 2.0 * tau * C[0][1] + tau * tau * C[1][1] + sy * sy;
+                    const double Syz = C[0][1] + tau * C[1][1];
+                    const double Szz = C[1][1] + vz;
+                    const double det2 = Syy * Szz - Syz * Syz;
+                    chi2 += (Szz * ry * ry - 2.0 * Syz * ry * rz + Syy * rz * rz) / det2;
+                    kalman_update(p, C, ry, rz, tau, sy * sy, vz);
+                    nused++;
+                    if (!(fabs(p[2]) < g->snp_max)) { status |= ST_STOP_SNP; break; }
+                }
+            }
+            if (l > 0) add_ms(p, C, g);
+        }
+    }
+    double pk[15];
+    pack(C, pk);
+    for (int k = 0; k < 5; k++) op[k * n + i] = p[k];
+    for (int k = 0; k < 15; k++) oc[k * n + i] = pk[k];
+    ox[i] = x;
+    osec[i] = sec;
+    ochi2[i] = chi2;
+    onused[i] = nused;
+    ostatus[i] = status;
+}
+
+int oracle_refit(const ocfg *g, int64_t n, const double *tp, const double *tx, const int32_t *tsec,
+                 const int32_t *idx, int64_t n_tkl, const double *ky, const double *kz, const uint32_t *kdr,
+                 int32_t n_threads, double *op, double *oc, double *ox, int32_t *osec, double *ochi2,
+                 int32_t *onused, uint32_t *ostatus)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; i++)
+        refit_one(g, i, n, tp, tx, tsec, idx, n_tkl, ky, kz, kdr, op, oc, ox, osec, ochi2, onused, ostatus);
     return 0;
 }
 

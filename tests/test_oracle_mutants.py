@@ -32,6 +32,11 @@ MUTANTS = {
     "beam_first_parent_state": ("*d = H[c->parent];", "*d = H[0];"),
     "beam_cost_not_carried": ("d->cost = c->cost;", ""),
     "beam_sum_holds_cost": ("d->chi2sum += c->chi2;", "d->chi2sum += c->cost;"),
+    "refit_no_scattering": ("            if (l > 0) add_ms(p, C, g);", ""),
+    "refit_chi2_cross_sign": ("(Szz * ry * ry - 2.0 * Syz * ry * rz + Syy * rz * rz) / det2",
+                              "(Szz * ry * ry + 2.0 * Syz * ry * rz + Syy * rz * rz) / det2"),
+    "refit_tilt_sign": ("const double ry = ky[j] - (p[0] + tau * (p[1] - kz[j]));",
+                        "const double ry = ky[j] - (p[0] - tau * (p[1] - kz[j]));"),
 }
 
 
@@ -49,6 +54,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_math.py"),
                         os.path.join(ROOT, "tests", "test_oracle_search.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_beam.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_beam.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_refit.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} passed every pin"
