@@ -64,6 +64,8 @@ extern "C" {
 #define TRD_TRK_NOT_PD 16u       /* float covariance lost positive definiteness */
 #define TRD_TRK_BAD_INPUT 32u    /* non-finite seed, bad sector/group, |snp| >= snp_max,
                                     or covariance not positive definite; copied through */
+#define TRD_TRK_REFIT_FEW 64u    /* trd_refit: fewer than refit_min tracklets; copied */
+#define TRD_TRK_REFIT_SKIP 128u  /* trd_refit: a tracklet more than one sector away was skipped */
 
 /* config flags */
 #define TRD_CFG_FAIL_ALLOC 1u     /* test hook: trd_create fails with TRD_ENOMEM */
@@ -128,6 +130,9 @@ typedef struct trd_config {
                                  search_lanes 0 or 1 and no TRD_CFG_PERSISTENT. */
     double chi2_penalty;      /* cost of a layer without a tracklet (n_hyp >= 1);
                                  >= chi2_max makes n_hyp = 1 the single best rule */
+    double refit_cov[5];      /* trd_refit: starting covariance, diagonal (y, z, sin phi,
+                                 tan lambda, q/pT); each > 0 */
+    int32_t refit_min;        /* trd_refit: tracks with fewer tracklets are copied (>= 1) */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */
@@ -200,6 +205,40 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
  * propagation and Kalman update).  Errors: TRD_EINVAL, TRD_ESTATE,
  * TRD_ENOMEM, TRD_EBUDGET, TRD_EDEVICE. */
 int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream);
+
+/* Matched tracks for trd_refit (device arrays of the state type, as written
+ * by trd_match). */
+typedef struct trd_refit_in {
+    const void *p;          /* [5][n] state after matching */
+    const void *x;          /* [n] its radius */
+    const int32_t *sector;  /* [n] its sector */
+    const int32_t *idx;     /* [6][n] matched tracklet per layer (input index), -1 if none */
+} trd_refit_in;
+
+/* Refit results (device arrays the caller owns). */
+typedef struct trd_refit_out {
+    void *p;           /* [5][n] state at layer 0 (the innermost layer reached) */
+    void *cov;         /* [15][n] its covariance, packed upper triangle */
+    void *x;           /* [n] */
+    int32_t *sector;   /* [n] */
+    void *chi2;        /* [n] sum of the predicted chi2 of the updates */
+    int32_t *n_used;   /* [n] tracklets used */
+    uint32_t *status;  /* [n] TRD_TRK_* bits of the refit */
+} trd_refit_out;
+
+/* TRD-only refit of matched tracks (Sect. 2, step 3: a refit from the outer
+ * detectors in which the TPC information is ignored).  For each track: the
+ * state of trd_match with its covariance replaced by diag(refit_cov), then
+ * inward over layers 5..0: propagation to the layer plane (sector hops as in
+ * the matching), for a matched tracklet a turn into its sector if that is a
+ * neighbour (else REFIT_SKIP), the step to its radius and the Kalman update,
+ * then the layer's scattering (not below layer 0).  The covariance is kept in
+ * double in every precision.  tkl: the tracklets the indices refer to (y, z,
+ * det_row of the trd_match input, n_tkl of them; group unused).  Tracks with
+ * fewer than refit_min valid indices are copied with REFIT_FEW, rejected
+ * states with BAD_INPUT.  Stream-ordered.  Errors: TRD_EINVAL, TRD_EDEVICE. */
+int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, int64_t n_tkl, int64_t n,
+              trd_refit_out *out, void *hip_stream);
 
 /* Fills *out with the context's sorted tracklets (valid until the next load
  * or destroy; read them on the load's stream).  Errors: TRD_EINVAL, TRD_ESTATE. */

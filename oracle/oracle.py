@@ -75,6 +75,8 @@ def lib():
         L.oracle_match.argtypes = ([C.POINTER(OCfg), C.c_int64, dp, dp, dp, ip, ip,
                                     C.c_int64, dp, dp, dp, up, ip, C.c_int32, C.c_int32, C.c_int32,
                                     ip, dp, dp, dp, ip, dp, dp, ip, up, up, ip, lp, dp, dp, dp, ip])
+        L.oracle_refit.argtypes = [C.POINTER(OCfg), C.c_int64, dp, dp, ip, ip, C.c_int64, dp, dp, up,
+                                   C.c_int32, dp, dp, dp, ip, dp, ip, up]
         L.oracle_propagate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
         L.oracle_rotate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
         L.oracle_add_ms.argtypes = [C.POINTER(OCfg), dp, dp]

@@ -19,6 +19,10 @@ TRD_OK, TRD_EINVAL, TRD_ENOMEM, TRD_EDEVICE, TRD_ESTATE, TRD_EBUDGET = 0, -1, -2
 TRD_PREC_FP64, TRD_PREC_FP32, TRD_PREC_FP32_COV64 = 0, 1, 2
 PRECISIONS = {"fp64": TRD_PREC_FP64, "fp32": TRD_PREC_FP32, "fp32_cov64": TRD_PREC_FP32_COV64}
 TRK_STOP_SNP, TRK_ROT_FAIL, TRK_OUT_OF_Z, TRK_FP64_FALLBACK, TRK_NOT_PD, TRK_BAD_INPUT = 1, 2, 4, 8, 16, 32
+TRK_REFIT_FEW, TRK_REFIT_SKIP = 64, 128
+# TRD-only refit defaults: starting covariance diag (cm^2, cm^2, -, -, (c/GeV)^2), fewest tracklets
+REFIT_COV = (1.0, 100.0, 1e-2, 1e-2, 1.0)
+REFIT_MIN = 4
 TRD_CFG_FAIL_ALLOC = 1
 TRD_CFG_FORCE_FALLBACK = 2
 TRD_CFG_PERSISTENT = 4
@@ -26,7 +30,7 @@ TRD_CFG_INPUT_ORDER = 8
 TRD_CFG_TIME_KERNEL = 16
 
 # every symbol include/trd.h declares
-EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_get_binning",
+EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_refit", "trd_get_binning",
            "trd_copy_binning", "trd_device_bytes", "trd_kernel_times", "trd_destroy", "trd_status_string")
 
 
@@ -50,6 +54,7 @@ class trd_config(C.Structure):
         ("snp_max", C.c_double),
         ("hbm_budget_bytes", C.c_uint64), ("block_size", C.c_int32), ("search_lanes", C.c_int32),
         ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
+        ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32),
     ]
 
 
@@ -67,6 +72,15 @@ class trd_results(C.Structure):
     _fields_ = [("idx", C.c_void_p), ("p", C.c_void_p), ("cov", C.c_void_p), ("x", C.c_void_p),
                 ("sector", C.c_void_p), ("chi2", C.c_void_p), ("chi2_layer", C.c_void_p),
                 ("n_match", C.c_void_p), ("status", C.c_void_p)]
+
+
+class trd_refit_in(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("x", C.c_void_p), ("sector", C.c_void_p), ("idx", C.c_void_p)]
+
+
+class trd_refit_out(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("cov", C.c_void_p), ("x", C.c_void_p), ("sector", C.c_void_p),
+                ("chi2", C.c_void_p), ("n_used", C.c_void_p), ("status", C.c_void_p)]
 
 
 class trd_binning_view(C.Structure):
@@ -89,6 +103,8 @@ def lib():
         L.trd_reserve.argtypes = [vp, C.c_int64, C.c_int32, C.c_int64]
         L.trd_load_tracklets.argtypes = [vp, C.POINTER(trd_tracklets), C.c_int64, C.c_int32, vp]
         L.trd_match.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
+        L.trd_refit.argtypes = [vp, C.POINTER(trd_refit_in), C.POINTER(trd_tracklets), C.c_int64, C.c_int64,
+                                C.POINTER(trd_refit_out), vp]
         L.trd_get_binning.argtypes = [vp, C.POINTER(trd_binning_view)]
         L.trd_copy_binning.argtypes = [vp, vp, vp, C.c_int64, vp]
         L.trd_device_bytes.argtypes = [vp]
@@ -138,6 +154,9 @@ def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, searc
     c.flags = int(flags)
     c.n_hyp = int(params.get("n_hyp", 0))
     c.chi2_penalty = float(params.get("chi2_penalty", params["chi2_max"]))
+    for k in range(5):
+        c.refit_cov[k] = float(params.get("refit_cov", REFIT_COV)[k])
+    c.refit_min = int(params.get("refit_min", REFIT_MIN))
     return c
 
 
@@ -160,6 +179,11 @@ def trd_load_tracklets(ctx, t: trd_tracklets, n, n_groups, stream=0):
 
 def trd_match(ctx, trk: trd_tracks, n, res: trd_results, stream=0):
     _check(lib().trd_match(ctx, C.byref(trk), int(n), C.byref(res), stream or None), "trd_match")
+
+
+def trd_refit(ctx, rin: trd_refit_in, tkl: trd_tracklets, n_tkl, n, rout: trd_refit_out, stream=0):
+    _check(lib().trd_refit(ctx, C.byref(rin), C.byref(tkl), int(n_tkl), int(n), C.byref(rout), stream or None),
+           "trd_refit")
 
 
 def trd_get_binning(ctx) -> trd_binning_view:
@@ -276,6 +300,24 @@ class Matcher:
         res = trd_results(*(None if out[k] is None else out[k].data_ptr() for k in
                             ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status")))
         trd_match(self.ctx, trk, n, res, _stream_handle(stream))
+        return out
+
+    def refit(self, matched, y, z, det_row, stream=None):
+        """TRD-only refit of the tracks of a match() result `matched` (p, x,
+        sector, idx) against the tracklets (y, z, det_row) they index."""
+        import torch
+        n = int(matched["x"].numel())
+        dev = torch.device("cuda", self.device)
+        f = self.fdtype
+        out = dict(p=torch.empty((5, n), dtype=f, device=dev), cov=torch.empty((15, n), dtype=f, device=dev),
+                   x=torch.empty(n, dtype=f, device=dev), sector=torch.empty(n, dtype=torch.int32, device=dev),
+                   chi2=torch.empty(n, dtype=f, device=dev), n_used=torch.empty(n, dtype=torch.int32, device=dev),
+                   status=torch.empty(n, dtype=torch.int32, device=dev))
+        rin = trd_refit_in(matched["p"].data_ptr(), matched["x"].data_ptr(), matched["sector"].data_ptr(),
+                           matched["idx"].data_ptr())
+        tkl = trd_tracklets(y.data_ptr(), z.data_ptr(), None, det_row.data_ptr(), None)
+        rout = trd_refit_out(*(out[k].data_ptr() for k in ("p", "cov", "x", "sector", "chi2", "n_used", "status")))
+        trd_refit(self.ctx, rin, tkl, y.numel(), n, rout, _stream_handle(stream))
         return out
 
     def binning(self, stream=None):

@@ -95,6 +95,9 @@ int check_config(const trd_config *c)
     }
     if (c->n_hyp > 0 && (c->search_lanes > 1 || (c->flags & TRD_CFG_PERSISTENT))) return TRD_EINVAL;
     if (c->n_hyp > 0 && !(c->chi2_penalty >= 0 && c->chi2_penalty < 1e30)) return TRD_EINVAL;
+    for (int k = 0; k < 5; k++)
+        if (!(c->refit_cov[k] > 0 && c->refit_cov[k] < 1e30)) return TRD_EINVAL;
+    if (c->refit_min < 1 || c->refit_min > 6) return TRD_EINVAL;
     return TRD_OK;
 }
 
@@ -472,6 +475,40 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size, ctx->cfg.search_lanes,
                  (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu, s);
     if (ord) launch_order_out(ctx->cfg.precision, io, ord_buf, s);
+    return launch_status();
+}
+
+int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, int64_t n_tkl, int64_t n,
+              trd_refit_out *out, void *hip_stream)
+{
+    if (!ctx || !in || !tkl || !out || n < 0 || n_tkl < 0) return TRD_EINVAL;
+    if (n == 0) return TRD_OK;
+    if (n >= (int64_t)INT32_MAX || n_tkl >= (int64_t)INT32_MAX) return TRD_EINVAL;
+    if (!in->p || !in->x || !in->sector || !in->idx || !out->p || !out->cov || !out->x || !out->sector ||
+        !out->chi2 || !out->n_used || !out->status)
+        return TRD_EINVAL;
+    if (n_tkl > 0 && (!tkl->y || !tkl->z || !tkl->det_row)) return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    RefitIO io{};
+    io.ip = in->p;
+    io.ix = in->x;
+    io.isec = in->sector;
+    io.idx = in->idx;
+    io.y = tkl->y;
+    io.z = tkl->z;
+    io.det_row = tkl->det_row;
+    io.n = n;
+    io.n_tkl = n_tkl;
+    for (int k = 0; k < 5; k++) io.cov0[k] = ctx->cfg.refit_cov[k];
+    io.min_tracklets = ctx->cfg.refit_min;
+    io.op = out->p;
+    io.oc = out->cov;
+    io.ox = out->x;
+    io.ochi2 = out->chi2;
+    io.osec = out->sector;
+    io.onused = out->n_used;
+    io.ost = out->status;
+    launch_refit(ctx->cfg.precision, ctx->gd, ctx->gf, io, (hipStream_t)hip_stream);
     return launch_status();
 }
 

@@ -13,7 +13,7 @@ constexpr int kDet = 540;
 
 // per-track status bits (same values as TRD_TRK_* of the public header)
 constexpr uint32_t kStopSnp = 1u, kRotFail = 2u, kOutOfZ = 4u, kFallback = 8u, kNotPD = 16u,
-                   kBadInput = 32u;
+                   kBadInput = 32u, kRefitFew = 64u, kRefitSkip = 128u;
 
 // Cell geometry of the tracklet binning; the key arithmetic runs in double
 // so that floor() sees the exact difference y - y_min (w is a power of two).
@@ -98,6 +98,23 @@ constexpr int kRowChi2 = 32;      // first chi2-per-layer entry of a long row
 // the order key holds the group and sector above 11 position bits
 constexpr int kOrderPosBits = 11;
 constexpr int32_t kMaxOrderGroups = (1 << (32 - kOrderPosBits)) / kSectors;
+
+// TRD-only refit: inputs and outputs (device arrays of the state type where
+// untyped; see trd_refit in the public header).
+struct RefitIO {
+    const void *ip, *ix;
+    const int32_t *isec, *idx;
+    const float *y, *z;
+    const uint32_t *det_row;
+    int64_t n, n_tkl;
+    double cov0[5];
+    int32_t min_tracklets;
+    void *op, *oc, *ox, *ochi2;
+    int32_t *osec, *onused;
+    uint32_t *ost;
+};
+void launch_refit(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf, const RefitIO &io,
+                  hipStream_t s);
 
 // Processing-order key of a seed: group and sector, then 16 cm in z and 4 cm
 // in y (clamped); rejected seeds get the largest key.

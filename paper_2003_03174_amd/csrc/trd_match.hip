@@ -396,10 +396,10 @@ __device__ __forceinline__ int load_track(const DevCfg<TS> &g, const MatchIO &io
     return bad ? 1 : 0;
 }
 
-// Propagation to the layer plane, sector hops, the layer's scattering.
-// False: the track stopped (status set).
+// Propagation to the layer plane and sector hops (predict adds the layer's
+// scattering).  False: the track stopped (status set).
 template <typename TS, typename TC>
-__device__ __forceinline__ bool predict(Trk<TS, TC> &T, int l, const DevCfg<TS> &g, uint32_t &status)
+__device__ __forceinline__ bool reach_plane(Trk<TS, TC> &T, int l, const DevCfg<TS> &g, uint32_t &status)
 {
     const TS xl = g.x_layer[l];
     if (!propagate(T, xl, g)) {
@@ -423,6 +423,13 @@ __device__ __forceinline__ bool predict(Trk<TS, TC> &T, int l, const DevCfg<TS> 
             return false;
         }
     }
+    return true;
+}
+
+template <typename TS, typename TC>
+__device__ __forceinline__ bool predict(Trk<TS, TC> &T, int l, const DevCfg<TS> &g, uint32_t &status)
+{
+    if (!reach_plane(T, l, g, status)) return false;
     add_ms(T, g);
     return true;
 }
@@ -1344,6 +1351,118 @@ void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &g
 
 namespace {
 
+// ---- TRD-only refit --------------------------------------------------------
+// One lane per track, inward over the layers: the matched track's state with
+// the covariance reset, propagation to each layer plane, a turn into the
+// tracklet's sector when it is a neighbour, the precise step and the update,
+// then the layer's scattering (none below layer 0).  Covariance in double.
+template <typename TS>
+__global__ void __launch_bounds__(256) k_refit(DevCfg<TS> g, RefitIO io)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= io.n) return;
+    const int64_t n = io.n;
+    const TS *ip = reinterpret_cast<const TS *>(io.ip);
+    Trk<TS, double> T;
+    T.y = ip[i];
+    T.z = ip[n + i];
+    T.s = ip[2 * n + i];
+    T.t = ip[3 * n + i];
+    T.c = ip[4 * n + i];
+    T.x = reinterpret_cast<const TS *>(io.ix)[i];
+    T.sec = io.isec[i];
+#pragma unroll
+    for (int k = 0; k < 15; k++) T.C[k] = 0.0;
+    T.C[YY] = io.cov0[0];
+    T.C[ZZ] = io.cov0[1];
+    T.C[SS] = io.cov0[2];
+    T.C[TT] = io.cov0[3];
+    T.C[CC] = io.cov0[4];
+    int idx[kLayers], nm = 0;
+#pragma unroll
+    for (int l = 0; l < kLayers; l++) {
+        idx[l] = io.idx[l * n + i];
+        nm += (idx[l] >= 0 && idx[l] < io.n_tkl) ? 1 : 0;
+    }
+    uint32_t status = 0;
+    int nused = 0;
+    double chi2 = 0.0;
+    bool bad = !(__builtin_isfinite(T.x) && T.sec >= 0 && T.sec < kSectors && __builtin_isfinite(T.y) &&
+                 __builtin_isfinite(T.z) && __builtin_isfinite(T.s) && __builtin_isfinite(T.t) &&
+                 __builtin_isfinite(T.c));
+    if (!bad) bad = !(fabs(T.s) < g.snp_max);
+    if (bad) {
+        status = kBadInput;
+    } else if (nm < io.min_tracklets) {
+        status = kRefitFew;
+    } else {
+        const double vz = double(g.pad_len) * double(g.pad_len) / 12.0;
+        for (int l = kLayers - 1; l >= 0; l--) {
+            if (!reach_plane(T, l, g, status)) break;
+            const int j = idx[l];
+            if (j >= 0 && j < io.n_tkl) {
+                const int det = (int)(io.det_row[j] >> 5), st = det / (kStacks * kLayers);
+                bool use = true;
+                if (st != T.sec) {
+                    const int d = (st - T.sec + kSectors) % kSectors;
+                    if (d == 1 || d == kSectors - 1) {
+                        if (!rotate(T, d == 1, g)) {
+                            status |= kRotFail;
+                            break;
+                        }
+                        T.sec = st;
+                        if (!propagate(T, g.x_layer[l], g)) {
+                            status |= kStopSnp;
+                            break;
+                        }
+                    } else {
+                        status |= kRefitSkip;
+                        use = false;
+                    }
+                }
+                if (use) {
+                    const TS dxj = g.dx[det];
+                    if (dxj != TS(0) && !propagate(T, g.x_layer[l] + dxj, g)) {
+                        status |= kStopSnp;
+                        break;
+                    }
+                    const TS tau = g.tilt[l];
+                    const TS yj = TS(io.y[j]), zj = TS(io.z[j]);
+                    const TS ry = yj - (T.y + tau * (T.z - zj));
+                    const TS rz = zj - T.z;
+                    const double sy = double(poly2(g.sigma_y, T.s)), tc = double(tau);
+                    const double Syy = T.C[YY] + 2.0 * tc * T.C[YZ] + tc * tc * T.C[ZZ] + sy * sy;
+                    const double Syz = T.C[YZ] + tc * T.C[ZZ];
+                    const double Szz = T.C[ZZ] + vz;
+                    const double dry = double(ry), drz = double(rz);
+                    chi2 += (Szz * dry * dry - 2.0 * Syz * dry * drz + Syy * drz * drz) / (Syy * Szz - Syz * Syz);
+                    if (!kalman_update(T, ry, rz, tau, sy * sy, vz)) status |= kNotPD;
+                    nused++;
+                    if (!(fabs(T.s) < g.snp_max)) {
+                        status |= kStopSnp;
+                        break;
+                    }
+                }
+            }
+            if (l > 0) add_ms(T, g);
+        }
+    }
+    TS *op = reinterpret_cast<TS *>(io.op);
+    TS *oc = reinterpret_cast<TS *>(io.oc);
+    op[i] = T.y;
+    op[n + i] = T.z;
+    op[2 * n + i] = T.s;
+    op[3 * n + i] = T.t;
+    op[4 * n + i] = T.c;
+#pragma unroll
+    for (int k = 0; k < 15; k++) oc[k * n + i] = TS(T.C[k]);
+    reinterpret_cast<TS *>(io.ox)[i] = T.x;
+    io.osec[i] = T.sec;
+    reinterpret_cast<TS *>(io.ochi2)[i] = TS(chi2);
+    io.onused[i] = nused;
+    io.ost[i] = status;
+}
+
 // input track i -> state row rank[i] (coalesced reads, one row per lane)
 template <typename TS>
 __global__ void __launch_bounds__(256) k_track_pack(MatchIO io, const uint32_t *rank, TS *rows)
@@ -1435,6 +1554,17 @@ void launch_order_in(int precision, MatchIO &io, int32_t n_groups, const TrackOr
         order_in<double>(io, n_groups, o, s);
     else
         order_in<float>(io, n_groups, o, s);
+}
+
+void launch_refit(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf, const RefitIO &io,
+                  hipStream_t s)
+{
+    if (io.n <= 0) return;
+    const unsigned grid = (unsigned)((io.n + 255) / 256);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_refit<double>, dim3(grid), dim3(256), 0, s, gd, io);
+    else
+        hipLaunchKernelGGL(k_refit<float>, dim3(grid), dim3(256), 0, s, gf, io);
 }
 
 void launch_order_out(int precision, const MatchIO &io, const TrackOrder &o, hipStream_t s)

@@ -1,0 +1,108 @@
+"""TRD-only refit (Sect. 2, step 3) on the HIP path against the FP64 oracle's
+refit, through the C ABI, on the same matched inputs."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2003_03174_amd import binding as B
+from paper_2003_03174_amd import synth
+from tests import parity_util as pu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DIAG = (0, 5, 9, 12, 14)
+
+
+def gpu_match_refit(w, prec, idx_edit=None):
+    d = B.device_inputs(synth.to_device_layout(w), prec)
+    m = B.Matcher(w["params"], prec)
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+    mo = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    if idx_edit is not None:
+        mo["idx"] = idx_edit(mo["idx"])
+    r = m.refit(mo, d["y"], d["z"], d["det_row"])
+    torch.cuda.synchronize()
+    matched = {k: mo[k].cpu().numpy() for k in ("p", "x", "sector", "idx")}
+    got = {k: v.cpu().numpy() for k, v in r.items()}
+    m.close()
+    return matched, got
+
+
+def compare(ref, got, prec, sel=None):
+    if sel is not None:
+        got = {k: (v[:, sel] if v.ndim == 2 else v[sel]) for k, v in got.items()}
+    st_g = got["status"].astype(np.int64) & ~pu.GPU_ONLY_BITS
+    assert np.array_equal(st_g, ref["status"].astype(np.int64))
+    assert np.array_equal(got["n_used"], ref["n_used"])
+    assert np.array_equal(got["sector"], ref["sector"])
+    ok = (ref["status"] & 32) == 0
+    d = np.abs(got["p"][:, ok].astype(np.float64) - ref["p"][:, ok])
+    if prec == "fp64":
+        e = d / np.maximum(np.abs(ref["p"][:, ok]), pu.FLOORS[:, None])
+        assert e.max() <= pu.STATE_TOL[prec], e.max(axis=1)
+    else:
+        # A TRD-only fit leaves q/pT and tan(lambda) loosely determined, so the
+        # float state's rounding is amplified there: bound it against the
+        # refit's own uncertainty (measured: <= 1e-4 sigma).
+        e = d / np.sqrt(ref["cov"][list(DIAG)][:, ok])
+        assert e.max() <= 1e-3, e.max(axis=1)
+    assert np.abs(got["x"][ok] - ref["x"][ok]).max() <= 1e-4 * (1 if prec != "fp64" else 1e-8)
+    gc, rc = got["cov"][:, ok].astype(np.float64), ref["cov"][:, ok]
+    worst, k = 0.0, 0
+    for i in range(5):
+        for j in range(i, 5):
+            den = np.sqrt(rc[DIAG[i]] * rc[DIAG[j]])
+            worst = max(worst, float((np.abs(gc[k] - rc[k]) / den).max()))
+            k += 1
+    assert worst <= (1e-3 if prec != "fp64" else 1e-10), worst
+    c_err = np.abs(got["chi2"][ok].astype(np.float64) - ref["chi2"][ok])
+    assert c_err.max() <= (pu.chi2_tol(prec) if prec != "fp64" else 1e-8), c_err.max()
+    return e.max(), worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
+def test_refit_small_frame(prec):
+    w = synth.generate("c1_small_fp64")
+    matched, got = gpu_match_refit(w, prec)
+    ref = O.refit(w["params"], matched, matched["idx"], w)
+    print(compare(ref, got, prec))
+    assert (got["n_used"] == 6).mean() > 0.8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_refit_tilt_misalignment(prec):
+    P = synth.default_params(tilt=synth.tilt_pm2deg())
+    P["dx_chamber"] = np.random.default_rng(21).uniform(-0.5, 0.5, 540)
+    g = synth.generate_group(np.random.default_rng(22), P, 3000, fake_ratio=0.5, ineff_frac=0.1)
+    w = synth._concat_groups([g], P)
+    matched, got = gpu_match_refit(w, prec)
+    ref = O.refit(P, matched, matched["idx"], w)
+    print(compare(ref, got, prec))
+
+
+def test_refit_distortion_batch_sampled():
+    w = synth.generate("c5_distortion_450k")
+    matched, got = gpu_match_refit(w, "fp32")
+    sel = np.sort(np.random.default_rng(5).choice(w["n_tracks"], 3000, replace=False))
+    sub = dict(p=matched["p"][:, sel], x=matched["x"][sel], sector=matched["sector"][sel])
+    ref = O.refit(w["params"], sub, matched["idx"][:, sel], w)
+    print(compare(ref, got, "fp32", sel=sel))
+
+
+def test_refit_few_and_bad():
+    w = synth.generate("c1_small_fp64")
+
+    def edit(idx):
+        idx = idx.clone()
+        idx[:3, ::2] = -1
+        idx[0, 1] = 10 ** 8       # out of range: not a tracklet
+        return idx
+
+    matched, got = gpu_match_refit(w, "fp32", idx_edit=edit)
+    ref = O.refit(w["params"], matched, matched["idx"], w)
+    compare(ref, got, "fp32")
+    few = ((matched["idx"] >= 0) & (matched["idx"] < w["n_tracklets"])).sum(axis=0) < 4
+    assert few.sum() > 100
+    assert np.all(got["status"][few] & B.TRK_REFIT_FEW)
+    assert np.array_equal(got["p"][:, few], matched["p"][:, few])
