@@ -167,17 +167,18 @@ def cpu_baseline(w, budget_s=12.0):
 
     P = w["params"]
     n = w["n_tracks"]
+    cores = int(O.lib().oracle_max_threads())
     t0 = time.perf_counter()
     O.bin_tracklets(P, w)
     t_bin = time.perf_counter() - t0
     probe = np.arange(0, n, max(1, n // 2000))
     t0 = time.perf_counter()
-    O.match(P, w, threads=0, track_slice=probe)
+    O.match(P, w, threads=cores, track_slice=probe)
     t_probe = max(time.perf_counter() - t0 - t_bin, 1e-6) / probe.size
     ns = int(min(n, max(probe.size, budget_s / t_probe)))
     sample = np.arange(0, n, max(1, n // ns))[:ns]
     t0 = time.perf_counter()
-    O.match(P, w, threads=0, track_slice=sample)
+    O.match(P, w, threads=cores, track_slice=sample)
     t_call = time.perf_counter() - t0
     per_trk = max(t_call - t_bin, 1e-9) / sample.size
     est = t_bin + per_trk * n
@@ -190,7 +191,7 @@ def cpu_baseline(w, budget_s=12.0):
     O.bin_tracklets(P, w)
     t_bin1 = time.perf_counter() - t0   # the binning is single-threaded in the oracle
     est1 = t_bin1 + max(t_one - t_bin1, 1e-9) / s1.size * n
-    return dict(value=n / est, unit="tracks/s", cores=int(O.lib().oracle_max_threads()), kind="oracle",
+    return dict(value=n / est, unit="tracks/s", cores=cores, kind="oracle",
                 value_1_thread=n / est1,
                 sample=(f"binning of all {w['n_tracklets']} tracklets ({t_bin:.2f} s) + matching of "
                         f"{sample.size} of {n} tracks (every {max(1, n // ns)}th, {t_call - t_bin:.2f} s), "
