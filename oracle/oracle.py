@@ -39,6 +39,17 @@ class OCfg(C.Structure):
         ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32), ("pad_", C.c_int32),
     ]
 
+class OTpc(C.Structure):
+    _fields_ = [("x_in", C.c_double), ("x_out", C.c_double), ("n_rows", C.c_int32),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("min_count", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+# sub-volumes of the residual maps: per sector 8 in x, 4 in y/x, 4 in z/x
+VOXELS = (8, 4, 4)
+VOXEL_MIN = 20
+
+
 # TRD-only refit defaults: starting covariance diag (cm^2, cm^2, -, -, (c/GeV)^2)
 REFIT_COV = (1.0, 100.0, 1e-2, 1e-2, 1.0)
 REFIT_MIN = 4
@@ -77,6 +88,9 @@ def lib():
                                     ip, dp, dp, dp, ip, dp, dp, ip, up, up, ip, lp, dp, dp, dp, ip])
         L.oracle_refit.argtypes = [C.POINTER(OCfg), C.c_int64, dp, dp, ip, ip, C.c_int64, dp, dp, up,
                                    C.c_int32, dp, dp, dp, ip, dp, ip, up]
+        L.oracle_residuals.argtypes = [C.POINTER(OCfg), C.POINTER(OTpc), C.c_int64, dp, dp, ip, up, lp, dp, dp,
+                                       ip, ip, dp]
+        L.oracle_voxel_solve.argtypes = [C.POINTER(OTpc), C.c_int64, dp, dp]
         L.oracle_propagate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
         L.oracle_rotate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
         L.oracle_add_ms.argtypes = [C.POINTER(OCfg), dp, dp]
@@ -213,6 +227,47 @@ def refit(params, tracks, idx, w, threads=0):
                         _ptr(o["chi2"], dp), _ptr(o["n_used"], ip_), _ptr(o["status"], up))
     assert rc == 0, rc
     return o
+
+
+def make_tpc(tpc, voxels=VOXELS, min_count=VOXEL_MIN):
+    t = OTpc()
+    t.x_in, t.x_out, t.n_rows = float(tpc["x_in"]), float(tpc["x_out"]), int(tpc["n_rows"])
+    t.nx, t.ny, t.nz = (int(v) for v in voxels)
+    t.min_count = int(min_count)
+    return t
+
+
+def residual_sums(params, ref, cl, voxels=VOXELS):
+    """Per-voxel sums [n_vox, 8] of the clusters' residuals against the
+    reference tracks (ref: p [5][n], x, sector, status), cl: tpc_clusters()."""
+    L = lib()
+    cfg = make_cfg(params)
+    t = make_tpc(cl["tpc"], voxels)
+    n = int(np.asarray(ref["x"]).size)
+    nvox = 18 * int(np.prod(voxels))
+    sums = np.zeros((nvox, 8))
+    rp, rx = _f64(ref["p"]), _f64(ref["x"])
+    rs = np.ascontiguousarray(ref["sector"], dtype=np.int32)
+    st = np.ascontiguousarray(ref["status"], dtype=np.uint32)
+    first = np.ascontiguousarray(cl["first"], dtype=np.int64)
+    cy, cz = _f64(cl["y"]), _f64(cl["z"])
+    crow = np.ascontiguousarray(cl["row"], dtype=np.int32)
+    csec = np.ascontiguousarray(cl["sector"], dtype=np.int32)
+    dp, ip_, up, lp = C.c_double, C.c_int32, C.c_uint32, C.c_int64
+    rc = L.oracle_residuals(C.byref(cfg), C.byref(t), n, _ptr(rp, dp), _ptr(rx, dp), _ptr(rs, ip_), _ptr(st, up),
+                            _ptr(first, lp), _ptr(cy, dp), _ptr(cz, dp), _ptr(crow, ip_), _ptr(csec, ip_),
+                            _ptr(sums, dp))
+    assert rc == 0
+    return sums
+
+
+def voxel_solve(sums, tpc, voxels=VOXELS, min_count=VOXEL_MIN):
+    """(dX, dY, dZ, n) per voxel from residual_sums()."""
+    t = make_tpc(tpc, voxels, min_count)
+    s = np.ascontiguousarray(sums, dtype=np.float64)
+    out = np.zeros((s.shape[0], 4))
+    lib().oracle_voxel_solve(C.byref(t), s.shape[0], _ptr(s, C.c_double), _ptr(out, C.c_double))
+    return out
 
 
 # ---- single steps -----------------------------------------------------------

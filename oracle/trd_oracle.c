@@ -1108,6 +1108,110 @@ int oracle_refit(const ocfg *g, int64_t n, const double *tp, const double *tx, c
     return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Residuals of TPC clusters against the reference tracks, per sub-volume  */
+/* (Sect. 2, steps 4 and 5)                                                */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    double x_in, x_out;         /* pad rows: x_r = x_out - r (x_out - x_in) / (n_rows - 1) */
+    int32_t n_rows;
+    int32_t nx, ny, nz;         /* voxels per sector: x, y/x over +-tan 10deg, z/x over +-1 */
+    int32_t min_count;          /* fewest clusters for a voxel's distortion */
+    int32_t pad_;
+} otpc;
+
+#define NSUM 8
+
+/* Readings where the paper is silent:
+ *   - the reference of a cluster is the reference track (the TRD-only refit
+ *     here; the ITS side is out of scope) propagated along its helix to the
+ *     cluster's pad row, turned into the cluster's sector when that is a
+ *     neighbour (clusters further away are left out);
+ *   - a cluster seen at row x was created at x - dX and displaced by
+ *     (dY, dZ), so to first order its residuals are
+ *     r_y = dY - dX tan(phi), r_z = dZ - dX tan(lambda)/cos(phi);
+ *   - a voxel is (sector, x bin, y/x bin, z/x bin) of the reference point;
+ *     per voxel (dX, dY, dZ) is the least-squares solution of those equations
+ *     over its clusters (unit weights), from 8 sums: n, sum t_y, sum t_z,
+ *     sum (t_y^2 + t_z^2), sum r_y, sum r_z, sum (t_y r_y + t_z r_z),
+ *     sum (r_y^2 + r_z^2);
+ *   - reference tracks with any status bit are left out. */
+static int64_t voxel_of(const otpc *t, int sec, double x, double y, double z)
+{
+    const double tan10 = tan(M_PI / NSEC);
+    double fx = (x - t->x_in) / (t->x_out - t->x_in) * t->nx;
+    double fy = (y / x / tan10 + 1.0) * 0.5 * t->ny;
+    double fz = (z / x + 1.0) * 0.5 * t->nz;
+    int ix = fx < 0 ? 0 : (fx >= t->nx ? t->nx - 1 : (int)fx);
+    int iy = fy < 0 ? 0 : (fy >= t->ny ? t->ny - 1 : (int)fy);
+    int iz = fz < 0 ? 0 : (fz >= t->nz ? t->nz - 1 : (int)fz);
+    return (((int64_t)sec * t->nx + ix) * t->ny + iy) * t->nz + iz;
+}
+
+int oracle_residuals(const ocfg *g, const otpc *t, int64_t n, const double *rp, const double *rx,
+                     const int32_t *rsec, const uint32_t *rstatus, const int64_t *first, const double *cy,
+                     const double *cz, const int32_t *crow, const int32_t *csec, double *sums)
+{
+    const double dphi = 2.0 * M_PI / NSEC;
+    const double step = (t->x_out - t->x_in) / (t->n_rows - 1);
+    for (int64_t i = 0; i < n; i++) {
+        if (rstatus[i] != 0) continue;
+        double p[5], x = rx[i];
+        int sec = rsec[i];
+        for (int k = 0; k < 5; k++) p[k] = rp[k * n + i];
+        for (int64_t c = first[i]; c < first[i + 1]; c++) {
+            const double xr = t->x_out - crow[c] * step;
+            if (csec[c] != sec) {
+                int d = (csec[c] - sec + NSEC) % NSEC;
+                if (d != 1 && d != NSEC - 1) continue;
+                if (!rotate(p, NULL, &x, d == 1 ? dphi : -dphi, g, NULL)) break;
+                sec = csec[c];
+            }
+            if (!propagate(p, NULL, &x, xr, g, NULL, NULL)) break;
+            const double f = sqrt(1.0 - p[2] * p[2]);
+            const double ty = p[2] / f, tz = p[3] / f;
+            const double ry = cy[c] - p[0], rz = cz[c] - p[1];
+            double *S = sums + NSUM * voxel_of(t, sec, xr, p[0], p[1]);
+            S[0] += 1.0;
+            S[1] += ty;
+            S[2] += tz;
+            S[3] += ty * ty + tz * tz;
+            S[4] += ry;
+            S[5] += rz;
+            S[6] += ty * ry + tz * rz;
+            S[7] += ry * ry + rz * rz;
+        }
+    }
+    return 0;
+}
+
+/* Per voxel (dX, dY, dZ, n) from the sums: the normal equations
+ *   [ n     0    -St ] [dY]   [  Sy ]
+ *   [ 0     n    -Sz ] [dZ] = [  Sz_r ]
+ *   [-St   -Sz   Stt ] [dX]   [ -Str ]
+ * solved by elimination; NaN below min_count or when singular. */
+int oracle_voxel_solve(const otpc *t, int64_t nvox, const double *sums, double *dist)
+{
+    for (int64_t v = 0; v < nvox; v++) {
+        const double *S = sums + NSUM * v;
+        double *o = dist + 4 * v;
+        o[3] = S[0];
+        o[0] = o[1] = o[2] = NAN;
+        if (S[0] < t->min_count) continue;
+        const double nn = S[0], st = S[1], sz = S[2], stt = S[3];
+        /* eliminate dY and dZ: dY = (Sy + st dX)/n, dZ = (Sz + sz dX)/n */
+        const double a = stt - (st * st + sz * sz) / nn;
+        const double b = -S[6] + (st * S[4] + sz * S[5]) / nn;
+        if (!(a > 1e-12 * stt)) continue;
+        const double dX = b / a;
+        o[0] = dX;
+        o[1] = (S[4] + st * dX) / nn;
+        o[2] = (S[5] + sz * dX) / nn;
+    }
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

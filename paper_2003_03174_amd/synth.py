@@ -389,7 +389,7 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
         n_tracks=n, p=inp, cov=cov, x=seed_x, sector=sec0.astype(np.int32),
         truth_seed=truth_seed, truth=truth, true_idx=true_idx,
         tkl_y=ty, tkl_z=tz, tkl_dy=tdy, tkl_det=tdet, tkl_row=trow,
-        tkl_label=tlab, tkl_layer=tlay, pt=pt, q=q, eta=eta,
+        tkl_label=tlab, tkl_layer=tlay, pt=pt, q=q, eta=eta, phi0=phi0.astype(np.float64),
     )
 
 
@@ -406,6 +406,8 @@ def _concat_groups(groups, params):
     out["sector"] = np.concatenate([g["sector"] for g in groups]).astype(np.int32)
     out["group"] = np.concatenate([np.full(g["n_tracks"], i, np.int32) for i, g in enumerate(groups)])
     out["pt"] = np.concatenate([g["pt"] for g in groups])
+    for k in ("q", "eta", "phi0"):
+        out[k] = np.concatenate([g[k] for g in groups])
     out["truth"] = {k: np.concatenate([g["truth"][k] for g in groups], axis=1) for k in groups[0]["truth"]}
     tk_off = np.cumsum([0] + [g["tkl_y"].size for g in groups])
     tr_off = np.cumsum([0] + [g["n_tracks"] for g in groups])
@@ -522,6 +524,105 @@ def serving_stream(seed=3, n_frames=100, rate_hz=200.0, median=15000, sigma=0.6)
     gaps = rng.exponential(1.0 / rate_hz, n_frames)
     sizes = np.maximum(1, np.round(rng.lognormal(math.log(median), sigma, n_frames))).astype(np.int64)
     return np.cumsum(gaps), sizes
+
+
+# ---------------------------------------------------------------------------
+# TPC clusters with space-charge distortions (Sect. 2: the calibration the
+# TRD matching serves)
+# ---------------------------------------------------------------------------
+# Readings: pad rows are planes at x_r in the sector frames, n_rows of them
+# evenly over [x_in, x_out]; an electron created at local x - dX reaches pad
+# row x and is seen displaced by (dY, dZ), with (dX, dY, dZ) a smooth field of
+# the sector-local position; clusters carry y, z at the row, float32-rounded,
+# with Gaussian noise sigma_cl.
+
+TPC_DEFAULT = dict(x_in=85.0, x_out=245.0, n_rows=64, sigma_cl=0.05, amp=(0.8, 2.0, 1.5))
+
+
+def tpc_field(x, y, z, amp=TPC_DEFAULT["amp"], x_in=85.0, x_out=245.0):
+    """Distortion (dX, dY, dZ) in cm at sector-local (x, y, z): largest at the
+    inner radius, smooth in y/x and z."""
+    u = (np.asarray(x) - x_in) / (x_out - x_in)
+    v = np.asarray(y) / (np.asarray(x) * math.tan(SECTOR_DPHI / 2))
+    w = np.asarray(z) / 250.0
+    ax, ay, az = amp
+    dX = ax * (1.0 - u) * (1.0 - w * w)
+    dY = ay * (1.0 - u) ** 2 * (1.0 + 0.3 * v) * (1.0 - 0.5 * w * w)
+    dZ = az * (1.0 - u) * w
+    return dX, dY, dZ
+
+
+def tpc_clusters(w, seed=0, *, tpc=None, field=True, noise_free=False):
+    """Clusters of every track of workload w on the TPC pad rows, outermost
+    first.  Returns a dict: first [n+1] (CSR), y, z (float32-valued), row,
+    sector per cluster, and the field at the true point (truth)."""
+    T = dict(TPC_DEFAULT, **(tpc or {}))
+    rng = np.random.default_rng(seed)
+    dt = np.float64
+    n = w["n_tracks"]
+    bz = w["params"]["bz"]
+    cu = -KAPPA * bz * (w["q"] / w["pt"])
+    tgl = np.sinh(w["eta"])
+    phi0 = w["phi0"]
+    xs = np.linspace(T["x_out"], T["x_in"], T["n_rows"])        # outermost first
+    tan10 = math.tan(SECTOR_DPHI / 2)
+    per_row = []
+    alive = np.ones(n, dtype=bool)
+    for r, xr in enumerate(xs):
+        # sector holding the crossing: start from the one at the cylinder r = xr
+        ok0, phi_pos, _, _ = _cross_cylinder(phi0, cu, dt(xr), dt)
+        sec = _sector_of(np.cos(phi_pos), np.sin(phi_pos))
+        zero = np.zeros(n)
+        ok, y, snp, csp, X1, Y1, arc, _ = _cross_plane(zero, zero, phi0, cu, _alpha(sec, dt), xr, dt)
+        for _ in range(2):
+            out = ok & (np.abs(y) > xr * tan10)
+            if not out.any():
+                break
+            sec = np.where(out, np.mod(sec + np.where(y > 0, 1, -1), N_SECTORS), sec)
+            ok2, y2, s2, c2, _, _, a2, _ = _cross_plane(zero, zero, phi0, cu, _alpha(sec, dt), xr, dt)
+            ok, y, snp, arc = np.where(out, ok2, ok), np.where(out, y2, y), np.where(out, s2, snp), \
+                np.where(out, a2, arc)
+        ok = ok0 & ok & (np.abs(y) <= xr * tan10) & (np.abs(snp) < 0.95)
+        z = tgl * arc
+        if field:
+            dX, dY, dZ = tpc_field(xr, y, z, T["amp"], T["x_in"], T["x_out"])
+        else:
+            dX = dY = dZ = np.zeros(n)
+        # the electron seen at row xr started at xr - dX on the same track
+        okd, yd, _, _, _, _, arcd, _ = _cross_plane(zero, zero, phi0, cu, _alpha(sec, dt), xr - dX, dt)
+        yc = yd + dY
+        zc = tgl * arcd + dZ
+        ok &= okd & (np.abs(zc) < 250.0)
+        if not noise_free:
+            yc = yc + rng.standard_normal(n) * T["sigma_cl"]
+            zc = zc + rng.standard_normal(n) * T["sigma_cl"]
+            yc = yc.astype(np.float32).astype(np.float64)
+            zc = zc.astype(np.float32).astype(np.float64)
+        alive &= ok   # a track that left the volume stays out
+        f = np.sqrt(np.maximum(1.0 - snp * snp, 1e-12))
+        per_row.append((alive.copy(), yc, zc, sec, dX, dY, dZ, y, z, snp / f, tgl / f))
+    cnt = np.zeros(n, dtype=np.int64)
+    for a, *_ in per_row:
+        cnt += a
+    first = np.zeros(n + 1, dtype=np.int64)
+    first[1:] = np.cumsum(cnt)
+    m = int(first[-1])
+    out = dict(first=first, y=np.zeros(m), z=np.zeros(m), row=np.zeros(m, np.int32),
+               sector=np.zeros(m, np.int32), dX=np.zeros(m), dY=np.zeros(m), dZ=np.zeros(m),
+               y_true=np.zeros(m), z_true=np.zeros(m), ty_true=np.zeros(m), tz_true=np.zeros(m),
+               x_rows=xs, tpc=T)
+    pos = first[:-1].copy()
+    for r, (a, yc, zc, sec, dX, dY, dZ, yt, zt, ty, tz) in enumerate(per_row):
+        ids = np.nonzero(a)[0]
+        k = pos[ids]
+        out["y"][k], out["z"][k] = yc[ids], zc[ids]
+        out["row"][k], out["sector"][k] = r, sec[ids]
+        out["dX"][k], out["dY"][k], out["dZ"][k] = dX[ids], dY[ids], dZ[ids]
+        out["y_true"][k], out["z_true"][k] = yt[ids], zt[ids]
+        out["ty_true"][k], out["tz_true"][k] = ty[ids], tz[ids]
+        pos[ids] += 1
+    out["n_clusters"] = m
+    return out
 
 
 DESCRIPTIONS = {

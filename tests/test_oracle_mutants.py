@@ -8,6 +8,7 @@ must fail.  The real oracle passes the same suite in the other tests.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -37,24 +38,46 @@ MUTANTS = {
                               "(Szz * ry * ry + 2.0 * Syz * ry * rz + Syy * rz * rz) / det2"),
     "refit_tilt_sign": ("const double ry = ky[j] - (p[0] + tau * (p[1] - kz[j]));",
                         "const double ry = ky[j] - (p[0] - tau * (p[1] - kz[j]));"),
+    "residual_stt_drops_z": ("S[3] += ty * ty + tz * tz;", "S[3] += ty * ty;"),
+    "residual_voxel_y_sign": ("double fy = (y / x / tan10 + 1.0) * 0.5 * t->ny;",
+                              "double fy = (-y / x / tan10 + 1.0) * 0.5 * t->ny;"),
+    "residual_solve_sign": ("const double b = -S[6] + (st * S[4] + sz * S[5]) / nn;",
+                            "const double b = S[6] - (st * S[4] + sz * S[5]) / nn;"),
 }
 
 
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_pins_catch_planted_mistake(name, tmp_path):
+PINS = ["test_oracle_math.py", "test_oracle_search.py", "test_oracle_beam.py", "test_oracle_refit.py",
+        "test_oracle_residuals.py"]
+
+
+def _run_mutant(name, tmp):
     src = open(SRC).read()
     a, b = MUTANTS[name]
-    assert src.count(a) >= 1, f"mutation site of {name} not found"
-    path = tmp_path / f"{name}.c"
-    lib = tmp_path / f"{name}.so"
-    path.write_text(src.replace(a, b, 1))
+    if src.count(a) < 1:
+        return "site"
+    path = os.path.join(tmp, f"{name}.c")
+    lib = os.path.join(tmp, f"{name}.so")
+    with open(path, "w") as f:
+        f.write(src.replace(a, b, 1))
     subprocess.run(["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-                    "-o", str(lib), str(path), "-lm"], check=True)
-    env = dict(os.environ, TRD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_math.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_search.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_beam.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_refit.py")],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, f"planted mistake {name} passed every pin"
+                    "-o", lib, path, "-lm"], check=True)
+    env = dict(os.environ, TRD_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] +
+                       [os.path.join(ROOT, "tests", p) for p in PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    return "caught" if r.returncode != 0 else "passed"
+
+
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    """Every planted mistake against the pin suite, several at a time."""
+    tmp = str(tmp_path_factory.mktemp("mutants"))
+    with ThreadPoolExecutor(max_workers=max(1, min(6, (os.cpu_count() or 2) - 1))) as ex:
+        futs = {n: ex.submit(_run_mutant, n, tmp) for n in MUTANTS}
+        return {n: f.result() for n, f in futs.items()}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, outcomes):
+    assert outcomes[name] != "site", f"mutation site of {name} not found"
+    assert outcomes[name] == "caught", f"planted mistake {name} passed every pin"
