@@ -133,6 +133,12 @@ typedef struct trd_config {
     double refit_cov[5];      /* trd_refit: starting covariance, diagonal (y, z, sin phi,
                                  tan lambda, q/pT); each > 0 */
     int32_t refit_min;        /* trd_refit: tracks with fewer tracklets are copied (>= 1) */
+    double tpc_x_in, tpc_x_out; /* residual maps: pad row r sits at x_out - r (x_out - x_in)
+                                 / (tpc_n_rows - 1), in the sector frame */
+    int32_t tpc_n_rows;       /* >= 2, <= 65535 */
+    int32_t vox_nx, vox_ny, vox_nz; /* voxels per sector in x, y/x (over +-tan 10 deg),
+                                 z/x (over +-1); 18 * nx * ny * nz <= 2048 */
+    int32_t vox_min;          /* fewest clusters for a voxel's distortion vector */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */
@@ -239,6 +245,45 @@ typedef struct trd_refit_out {
  * states with BAD_INPUT.  Stream-ordered.  Errors: TRD_EINVAL, TRD_EDEVICE. */
 int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, int64_t n_tkl, int64_t n,
               trd_refit_out *out, void *hip_stream);
+
+/* Reference tracks for the residual maps (device arrays of the state type,
+ * e.g. a trd_refit_out): state, radius, sector, status (tracks with any
+ * status bit are left out). */
+typedef struct trd_reference {
+    const void *p;           /* [5][n] */
+    const void *x;           /* [n] */
+    const int32_t *sector;   /* [n] */
+    const uint32_t *status;  /* [n] */
+} trd_reference;
+
+/* TPC clusters of the reference tracks (device arrays). */
+typedef struct trd_tpc_clusters {
+    const float *y, *z;        /* [n_cl] cluster position at its pad row, sector frame */
+    const uint32_t *row_sec;   /* [n_cl] (sector << 16) | pad row */
+    const int64_t *first;      /* [n + 1] clusters of track i: first[i] .. first[i+1]-1,
+                                  outermost row first */
+} trd_tpc_clusters;
+
+/* Residual maps (Sect. 2, steps 4-5): each reference track is carried along
+ * its helix to its clusters' pad rows (turning into a neighbouring sector
+ * when the cluster lies there; clusters further away are left out), and the
+ * residuals r_y = y_cl - y, r_z = z_cl - z with the track angles
+ * t_y = tan(phi), t_z = tan(lambda)/cos(phi) are summed per voxel
+ * (sector, x, y/x, z/x of the track point) as n, sum t_y, sum t_z,
+ * sum (t_y^2 + t_z^2), sum r_y, sum r_z, sum (t_y r_y + t_z r_z),
+ * sum (r_y^2 + r_z^2).  sums: device [n_vox][8] doubles, ADDED to (zero them
+ * before the first batch of a map; several batches accumulate), n_vox =
+ * 18 * vox_nx * vox_ny * vox_nz.  Stream-ordered; the summation order is not
+ * fixed, so results vary in the last bits.  Errors: TRD_EINVAL, TRD_EDEVICE. */
+int trd_residual_sums(trd_ctx *ctx, const trd_reference *ref, const trd_tpc_clusters *cl, int64_t n,
+                      int64_t n_cl, double *sums, void *hip_stream);
+
+/* Per voxel distortion vector from the sums: dist[v] = (dX, dY, dZ, n), the
+ * least-squares solution of r_y = dY - dX t_y, r_z = dZ - dX t_z (a cluster
+ * seen at row x was created at x - dX and displaced by dY, dZ); NaN for voxels
+ * with fewer than vox_min clusters.  dist: device [n_vox][4] floats.
+ * Stream-ordered.  Errors: TRD_EINVAL, TRD_EDEVICE. */
+int trd_voxel_solve(trd_ctx *ctx, const double *sums, float *dist, void *hip_stream);
 
 /* Fills *out with the context's sorted tracklets (valid until the next load
  * or destroy; read them on the load's stream).  Errors: TRD_EINVAL, TRD_ESTATE. */

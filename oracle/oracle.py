@@ -45,8 +45,8 @@ class OTpc(C.Structure):
                 ("pad_", C.c_int32)]
 
 
-# sub-volumes of the residual maps: per sector 8 in x, 4 in y/x, 4 in z/x
-VOXELS = (8, 4, 4)
+# sub-volumes of the residual maps: per sector 8 in x, 4 in y/x, 3 in z/x
+VOXELS = (8, 4, 3)
 VOXEL_MIN = 20
 
 

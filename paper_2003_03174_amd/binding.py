@@ -23,6 +23,10 @@ TRK_REFIT_FEW, TRK_REFIT_SKIP = 64, 128
 # TRD-only refit defaults: starting covariance diag (cm^2, cm^2, -, -, (c/GeV)^2), fewest tracklets
 REFIT_COV = (1.0, 100.0, 1e-2, 1e-2, 1.0)
 REFIT_MIN = 4
+# residual maps: TPC pad rows and voxels per sector (x, y/x, z/x), fewest clusters per voxel
+TPC_ROWS = dict(x_in=85.0, x_out=245.0, n_rows=64)
+VOXELS = (8, 4, 3)
+VOXEL_MIN = 20
 TRD_CFG_FAIL_ALLOC = 1
 TRD_CFG_FORCE_FALLBACK = 2
 TRD_CFG_PERSISTENT = 4
@@ -30,8 +34,9 @@ TRD_CFG_INPUT_ORDER = 8
 TRD_CFG_TIME_KERNEL = 16
 
 # every symbol include/trd.h declares
-EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_refit", "trd_get_binning",
-           "trd_copy_binning", "trd_device_bytes", "trd_kernel_times", "trd_destroy", "trd_status_string")
+EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_refit", "trd_residual_sums",
+           "trd_voxel_solve", "trd_get_binning", "trd_copy_binning", "trd_device_bytes", "trd_kernel_times",
+           "trd_destroy", "trd_status_string")
 
 
 class TrdError(RuntimeError):
@@ -55,6 +60,8 @@ class trd_config(C.Structure):
         ("hbm_budget_bytes", C.c_uint64), ("block_size", C.c_int32), ("search_lanes", C.c_int32),
         ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
         ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32),
+        ("tpc_x_in", C.c_double), ("tpc_x_out", C.c_double), ("tpc_n_rows", C.c_int32),
+        ("vox_nx", C.c_int32), ("vox_ny", C.c_int32), ("vox_nz", C.c_int32), ("vox_min", C.c_int32),
     ]
 
 
@@ -83,6 +90,14 @@ class trd_refit_out(C.Structure):
                 ("chi2", C.c_void_p), ("n_used", C.c_void_p), ("status", C.c_void_p)]
 
 
+class trd_reference(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("x", C.c_void_p), ("sector", C.c_void_p), ("status", C.c_void_p)]
+
+
+class trd_tpc_clusters(C.Structure):
+    _fields_ = [("y", C.c_void_p), ("z", C.c_void_p), ("row_sec", C.c_void_p), ("first", C.c_void_p)]
+
+
 class trd_binning_view(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("sorted", C.c_void_p),
                 ("n_cells", C.c_int64), ("n_tracklets", C.c_int64)]
@@ -105,6 +120,9 @@ def lib():
         L.trd_match.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
         L.trd_refit.argtypes = [vp, C.POINTER(trd_refit_in), C.POINTER(trd_tracklets), C.c_int64, C.c_int64,
                                 C.POINTER(trd_refit_out), vp]
+        L.trd_residual_sums.argtypes = [vp, C.POINTER(trd_reference), C.POINTER(trd_tpc_clusters), C.c_int64,
+                                        C.c_int64, vp, vp]
+        L.trd_voxel_solve.argtypes = [vp, vp, vp, vp]
         L.trd_get_binning.argtypes = [vp, C.POINTER(trd_binning_view)]
         L.trd_copy_binning.argtypes = [vp, vp, vp, C.c_int64, vp]
         L.trd_device_bytes.argtypes = [vp]
@@ -157,6 +175,10 @@ def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, searc
     for k in range(5):
         c.refit_cov[k] = float(params.get("refit_cov", REFIT_COV)[k])
     c.refit_min = int(params.get("refit_min", REFIT_MIN))
+    tpc = params.get("tpc", TPC_ROWS)
+    c.tpc_x_in, c.tpc_x_out, c.tpc_n_rows = float(tpc["x_in"]), float(tpc["x_out"]), int(tpc["n_rows"])
+    c.vox_nx, c.vox_ny, c.vox_nz = (int(v) for v in params.get("voxels", VOXELS))
+    c.vox_min = int(params.get("vox_min", VOXEL_MIN))
     return c
 
 
@@ -184,6 +206,15 @@ def trd_match(ctx, trk: trd_tracks, n, res: trd_results, stream=0):
 def trd_refit(ctx, rin: trd_refit_in, tkl: trd_tracklets, n_tkl, n, rout: trd_refit_out, stream=0):
     _check(lib().trd_refit(ctx, C.byref(rin), C.byref(tkl), int(n_tkl), int(n), C.byref(rout), stream or None),
            "trd_refit")
+
+
+def trd_residual_sums(ctx, ref: trd_reference, cl: trd_tpc_clusters, n, n_cl, sums_ptr, stream=0):
+    _check(lib().trd_residual_sums(ctx, C.byref(ref), C.byref(cl), int(n), int(n_cl), sums_ptr, stream or None),
+           "trd_residual_sums")
+
+
+def trd_voxel_solve(ctx, sums_ptr, dist_ptr, stream=0):
+    _check(lib().trd_voxel_solve(ctx, sums_ptr, dist_ptr, stream or None), "trd_voxel_solve")
 
 
 def trd_get_binning(ctx) -> trd_binning_view:
@@ -319,6 +350,28 @@ class Matcher:
         rout = trd_refit_out(*(out[k].data_ptr() for k in ("p", "cov", "x", "sector", "chi2", "n_used", "status")))
         trd_refit(self.ctx, rin, tkl, y.numel(), n, rout, _stream_handle(stream))
         return out
+
+    def residual_map(self, ref, cl, sums=None, stream=None):
+        """Voxel sums [n_vox, 8] (float64, added to `sums` if given) and the
+        distortion vectors [n_vox, 4] of the clusters `cl` (device tensors y,
+        z float32, row_sec int32, first int64) against the reference tracks
+        `ref` (p, x, sector, status; e.g. a refit() result)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        nx, ny, nz = self.params.get("voxels", VOXELS)
+        nv = 18 * int(nx) * int(ny) * int(nz)
+        if sums is None:
+            sums = torch.zeros((nv, 8), dtype=torch.float64, device=dev)
+        n = int(ref["x"].numel())
+        r = trd_reference(ref["p"].data_ptr(), ref["x"].data_ptr(), ref["sector"].data_ptr(),
+                          ref["status"].data_ptr())
+        c = trd_tpc_clusters(cl["y"].data_ptr(), cl["z"].data_ptr(), cl["row_sec"].data_ptr(),
+                             cl["first"].data_ptr())
+        h = _stream_handle(stream)
+        trd_residual_sums(self.ctx, r, c, n, cl["y"].numel(), C.c_void_p(sums.data_ptr()), h)
+        dist = torch.empty((nv, 4), dtype=torch.float32, device=dev)
+        trd_voxel_solve(self.ctx, C.c_void_p(sums.data_ptr()), C.c_void_p(dist.data_ptr()), h)
+        return sums, dist
 
     def binning(self, stream=None):
         """(offsets[n_cells+1] uint32 as int32, sorted[n_valid, 4] float32) copies."""

@@ -98,6 +98,10 @@ int check_config(const trd_config *c)
     for (int k = 0; k < 5; k++)
         if (!(c->refit_cov[k] > 0 && c->refit_cov[k] < 1e30)) return TRD_EINVAL;
     if (c->refit_min < 1 || c->refit_min > 6) return TRD_EINVAL;
+    if (!(c->tpc_x_in > 0 && c->tpc_x_out > c->tpc_x_in && c->tpc_x_out < 1e4) || c->tpc_n_rows < 2 ||
+        c->tpc_n_rows > 65535 || c->vox_nx < 1 || c->vox_ny < 1 || c->vox_nz < 1 || c->vox_min < 1)
+        return TRD_EINVAL;
+    if ((int64_t)TRD_N_SECTORS * c->vox_nx * c->vox_ny * c->vox_nz > kMaxVoxels) return TRD_EINVAL;
     return TRD_OK;
 }
 
@@ -509,6 +513,47 @@ int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, in
     io.onused = out->n_used;
     io.ost = out->status;
     launch_refit(ctx->cfg.precision, ctx->gd, ctx->gf, io, (hipStream_t)hip_stream);
+    return launch_status();
+}
+
+int trd_residual_sums(trd_ctx *ctx, const trd_reference *ref, const trd_tpc_clusters *cl, int64_t n,
+                      int64_t n_cl, double *sums, void *hip_stream)
+{
+    if (!ctx || !ref || !cl || !sums || n < 0 || n_cl < 0) return TRD_EINVAL;
+    if (n == 0) return TRD_OK;
+    if (!ref->p || !ref->x || !ref->sector || !ref->status || !cl->first) return TRD_EINVAL;
+    if (n_cl > 0 && (!cl->y || !cl->z || !cl->row_sec)) return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    const trd_config &c = ctx->cfg;
+    ResidualIO io{};
+    io.rp = ref->p;
+    io.rx = ref->x;
+    io.rsec = ref->sector;
+    io.rstatus = ref->status;
+    io.cy = cl->y;
+    io.cz = cl->z;
+    io.row_sec = cl->row_sec;
+    io.first = cl->first;
+    io.n = n;
+    io.sums = sums;
+    io.x_in = c.tpc_x_in;
+    io.x_out = c.tpc_x_out;
+    io.n_rows = c.tpc_n_rows;
+    io.nx = c.vox_nx;
+    io.ny = c.vox_ny;
+    io.nz = c.vox_nz;
+    io.nvox = TRD_N_SECTORS * c.vox_nx * c.vox_ny * c.vox_nz;
+    launch_residual_sums(c.precision, ctx->gd, ctx->gf, io, ctx->n_cu, (hipStream_t)hip_stream);
+    return launch_status();
+}
+
+int trd_voxel_solve(trd_ctx *ctx, const double *sums, float *dist, void *hip_stream)
+{
+    if (!ctx || !sums || !dist) return TRD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    const trd_config &c = ctx->cfg;
+    launch_voxel_solve(sums, TRD_N_SECTORS * c.vox_nx * c.vox_ny * c.vox_nz, c.vox_min, dist,
+                       (hipStream_t)hip_stream);
     return launch_status();
 }
 

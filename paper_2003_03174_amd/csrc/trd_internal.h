@@ -116,6 +116,26 @@ struct RefitIO {
 void launch_refit(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf, const RefitIO &io,
                   hipStream_t s);
 
+// Residual maps: reference tracks, TPC clusters, voxel sums (see
+// trd_residual_sums in the public header).
+constexpr int kVoxelSums = 8;
+constexpr int kMaxVoxels = 2048;  // the per-workgroup LDS copy of the sums: 64 KB
+struct ResidualIO {
+    const void *rp, *rx;
+    const int32_t *rsec;
+    const uint32_t *rstatus;
+    const float *cy, *cz;
+    const uint32_t *row_sec;
+    const int64_t *first;
+    int64_t n;
+    double *sums;
+    double x_in, x_out;
+    int32_t n_rows, nx, ny, nz, nvox;
+};
+void launch_residual_sums(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
+                          const ResidualIO &io, int n_cu, hipStream_t s);
+void launch_voxel_solve(const double *sums, int nvox, int min_count, float *dist, hipStream_t s);
+
 // Processing-order key of a seed: group and sector, then 16 cm in z and 4 cm
 // in y (clamped); rejected seeds get the largest key.
 template <typename TS>

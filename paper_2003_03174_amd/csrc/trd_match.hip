@@ -1463,6 +1463,129 @@ __global__ void __launch_bounds__(256) k_refit(DevCfg<TS> g, RefitIO io)
     io.ost[i] = status;
 }
 
+// ---- residual maps of TPC clusters ---------------------------------------
+// Position-only forms of the helix step and the frame turn (same arithmetic
+// as propagate and rotate, without the covariance).
+template <typename TS>
+__device__ __forceinline__ bool step_state(TS &x, TS &y, TS &z, TS &s, TS t, TS c, TS x2, const DevCfg<TS> &g)
+{
+    const TS dx = x2 - x;
+    const TS cu = g.k_curv * c;
+    const TS s1 = s;
+    const TS s2 = s1 + cu * dx;
+    if (!(fabs(s2) < g.snp_max)) return false;
+    const TS f1 = sqrt(TS(1) - s1 * s1);
+    const TS f2 = sqrt(TS(1) - s2 * s2);
+    const TS dy = div_(dx * (s1 + s2), f1 + f2);
+    const TS chord = sqrt(dx * dx + dy * dy);
+    const TS h = TS(0.5) * fabs(cu) * chord;
+    const TS aoh = h > TS(0) ? div_(TS(asin(h)), h) : TS(1);
+    const TS arc = (dx >= TS(0) ? chord : -chord) * aoh;
+    y += dy;
+    z += t * arc;
+    s = s2;
+    x = x2;
+    return true;
+}
+
+template <typename TS>
+__device__ __forceinline__ bool turn_state(TS &x, TS &y, TS &s, bool up, const DevCfg<TS> &g)
+{
+    const TS ca = g.cos_sector, sa = up ? g.sin_sector : -g.sin_sector;
+    const TS f = sqrt(TS(1) - s * s);
+    const TS s1 = s * ca - f * sa;
+    const TS f1 = f * ca + s * sa;
+    if (!(f1 > TS(0))) return false;
+    const TS x1 = x * ca + y * sa;
+    const TS y1 = -x * sa + y * ca;
+    x = x1;
+    y = y1;
+    s = s1;
+    return true;
+}
+
+// One lane per reference track, walking its clusters inward; the 8 sums of
+// every voxel are kept per workgroup in LDS (float) and added to the global
+// double sums at the end.  Grid-stride over the tracks.
+template <typename TS>
+__global__ void __launch_bounds__(256) k_residual_sums(DevCfg<TS> g, ResidualIO io)
+{
+    extern __shared__ float ls[];
+    const int nsum = io.nvox * kVoxelSums;
+    for (int k = threadIdx.x; k < nsum; k += blockDim.x) ls[k] = 0.f;
+    __syncthreads();
+    const TS *rp = reinterpret_cast<const TS *>(io.rp);
+    const TS *rx = reinterpret_cast<const TS *>(io.rx);
+    const TS step = TS(io.x_out - io.x_in) / TS(io.n_rows - 1);
+    const TS fxs = TS(io.nx) / TS(io.x_out - io.x_in);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < io.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (io.rstatus[i] != 0) continue;
+        TS y = rp[i], z = rp[io.n + i], sn = rp[2 * io.n + i], t = rp[3 * io.n + i], c = rp[4 * io.n + i];
+        TS x = rx[i];
+        int sec = io.rsec[i];
+        if (sec < 0 || sec >= kSectors) continue;
+        for (int64_t k = io.first[i]; k < io.first[i + 1]; k++) {
+            const uint32_t rs = io.row_sec[k];
+            const int csec = (int)(rs >> 16), row = (int)(rs & 0xffffu);
+            if (csec >= kSectors || row >= io.n_rows) continue;
+            const TS xr = TS(io.x_out) - TS(row) * step;
+            if (csec != sec) {
+                const int d = (csec - sec + kSectors) % kSectors;
+                if (d != 1 && d != kSectors - 1) continue;
+                if (!turn_state(x, y, sn, d == 1, g)) break;
+                sec = csec;
+            }
+            if (!step_state(x, y, z, sn, t, c, xr, g)) break;
+            const TS f = sqrt(TS(1) - sn * sn);
+            const TS ty = div_(sn, f), tz = div_(t, f);
+            const TS ry = TS(io.cy[k]) - y, rz = TS(io.cz[k]) - z;
+            const TS fx = (xr - TS(io.x_in)) * fxs;
+            const TS fy = (div_(div_(y, xr), g.tan_half_sector) + TS(1)) * TS(0.5) * TS(io.ny);
+            const TS fz = (div_(z, xr) + TS(1)) * TS(0.5) * TS(io.nz);
+            const int ix = fx < TS(0) ? 0 : (fx >= TS(io.nx) ? io.nx - 1 : (int)fx);
+            const int iy = fy < TS(0) ? 0 : (fy >= TS(io.ny) ? io.ny - 1 : (int)fy);
+            const int iz = fz < TS(0) ? 0 : (fz >= TS(io.nz) ? io.nz - 1 : (int)fz);
+            float *S = ls + kVoxelSums * (((sec * io.nx + ix) * io.ny + iy) * io.nz + iz);
+            atomicAdd(&S[0], 1.f);
+            atomicAdd(&S[1], float(ty));
+            atomicAdd(&S[2], float(tz));
+            atomicAdd(&S[3], float(ty * ty + tz * tz));
+            atomicAdd(&S[4], float(ry));
+            atomicAdd(&S[5], float(rz));
+            atomicAdd(&S[6], float(ty * ry + tz * rz));
+            atomicAdd(&S[7], float(ry * ry + rz * rz));
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nsum; k += blockDim.x) {
+        const float v = ls[k];
+        if (v != 0.f) atomicAdd(&io.sums[k], (double)v);
+    }
+}
+
+// Per voxel (dX, dY, dZ, n): the least-squares solution of
+// r_y = dY - dX tan(phi), r_z = dZ - dX tan(lambda)/cos(phi) from its sums.
+__global__ void __launch_bounds__(256) k_voxel_solve(const double *sums, int nvox, int min_count, float *dist)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    const double *S = sums + kVoxelSums * v;
+    float4 o = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), float(S[0]));
+    const double nn = S[0], st = S[1], sz = S[2], stt = S[3];
+    if (nn >= min_count) {
+        const double a = stt - (st * st + sz * sz) / nn;
+        const double b = -S[6] + (st * S[4] + sz * S[5]) / nn;
+        if (a > 1e-12 * stt) {
+            const double dX = b / a;
+            o.x = float(dX);
+            o.y = float((S[4] + st * dX) / nn);
+            o.z = float((S[5] + sz * dX) / nn);
+        }
+    }
+    reinterpret_cast<float4 *>(dist)[v] = o;
+}
+
 // input track i -> state row rank[i] (coalesced reads, one row per lane)
 template <typename TS>
 __global__ void __launch_bounds__(256) k_track_pack(MatchIO io, const uint32_t *rank, TS *rows)
@@ -1565,6 +1688,27 @@ void launch_refit(int precision, const DevCfg<double> &gd, const DevCfg<float> &
         hipLaunchKernelGGL(k_refit<double>, dim3(grid), dim3(256), 0, s, gd, io);
     else
         hipLaunchKernelGGL(k_refit<float>, dim3(grid), dim3(256), 0, s, gf, io);
+}
+
+void launch_residual_sums(int precision, const DevCfg<double> &gd, const DevCfg<float> &gf,
+                          const ResidualIO &io, int n_cu, hipStream_t s)
+{
+    if (io.n <= 0) return;
+    const size_t lds = sizeof(float) * (size_t)io.nvox * kVoxelSums;
+    int64_t blocks = (io.n + 255) / 256;
+    const int64_t cap = 2 * (int64_t)(n_cu > 0 ? n_cu : 1);
+    if (blocks > cap) blocks = cap;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_residual_sums<double>, dim3((unsigned)blocks), dim3(256), lds, s, gd, io);
+    else
+        hipLaunchKernelGGL(k_residual_sums<float>, dim3((unsigned)blocks), dim3(256), lds, s, gf, io);
+}
+
+void launch_voxel_solve(const double *sums, int nvox, int min_count, float *dist, hipStream_t s)
+{
+    if (nvox <= 0) return;
+    hipLaunchKernelGGL(k_voxel_solve, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, s, sums, nvox,
+                       min_count, dist);
 }
 
 void launch_order_out(int precision, const MatchIO &io, const TrackOrder &o, hipStream_t s)

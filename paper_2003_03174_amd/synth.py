@@ -552,18 +552,20 @@ def tpc_field(x, y, z, amp=TPC_DEFAULT["amp"], x_in=85.0, x_out=245.0):
     return dX, dY, dZ
 
 
-def tpc_clusters(w, seed=0, *, tpc=None, field=True, noise_free=False):
-    """Clusters of every track of workload w on the TPC pad rows, outermost
-    first.  Returns a dict: first [n+1] (CSR), y, z (float32-valued), row,
-    sector per cluster, and the field at the true point (truth)."""
+def tpc_clusters(w, seed=0, *, tpc=None, field=True, noise_free=False, tracks=None):
+    """Clusters of the tracks of workload w (all, or the index array
+    `tracks`) on the TPC pad rows, outermost first.  Returns a dict: first
+    [n+1] (CSR), y, z (float32-valued), row, sector per cluster, and the field
+    and track at the true point (truth)."""
     T = dict(TPC_DEFAULT, **(tpc or {}))
     rng = np.random.default_rng(seed)
     dt = np.float64
-    n = w["n_tracks"]
+    sel = np.arange(w["n_tracks"]) if tracks is None else np.asarray(tracks)
+    n = int(sel.size)
     bz = w["params"]["bz"]
-    cu = -KAPPA * bz * (w["q"] / w["pt"])
-    tgl = np.sinh(w["eta"])
-    phi0 = w["phi0"]
+    cu = -KAPPA * bz * (w["q"][sel] / w["pt"][sel])
+    tgl = np.sinh(w["eta"][sel])
+    phi0 = w["phi0"][sel]
     xs = np.linspace(T["x_out"], T["x_in"], T["n_rows"])        # outermost first
     tan10 = math.tan(SECTOR_DPHI / 2)
     per_row = []

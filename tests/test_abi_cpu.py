@@ -29,7 +29,8 @@ def test_library_exports_every_declared_function():
 def test_config_struct_size_matches_header_layout():
     # 2 ints + 12 doubles + 2 doubles + 4 ints + 3 doubles + 540 + 3 + 3+3+1 + 4 doubles + u64 + 2 ints
     # + n_hyp (int, padded) + chi2_penalty + refit_cov[5] + refit_min (int, padded)
-    assert C.sizeof(B.trd_config) == 8 + 8 * 12 + 16 + 16 + 24 + 8 * 540 + 24 + 56 + 32 + 8 + 8 + 16 + 48
+    # + tpc_x_in, tpc_x_out + 5 ints (padded)
+    assert C.sizeof(B.trd_config) == 8 + 8 * 12 + 16 + 16 + 24 + 8 * 540 + 24 + 56 + 32 + 8 + 8 + 16 + 48 + 40
 
 
 def test_status_strings():
@@ -63,6 +64,10 @@ def _cfg(**kw):
     lambda c: c.refit_cov.__setitem__(3, 0.0),
     lambda c: setattr(c, "refit_min", 0),
     lambda c: setattr(c, "refit_min", 7),
+    lambda c: setattr(c, "tpc_n_rows", 1),
+    lambda c: setattr(c, "tpc_x_out", 50.0),
+    lambda c: setattr(c, "vox_nx", 16),          # 18 * 16 * 4 * 3 > 2048 voxels
+    lambda c: setattr(c, "vox_min", 0),
     lambda c: c.x_layer.__setitem__(2, float("nan")),
 ])
 def test_create_rejects_bad_config(mutate):
