@@ -198,6 +198,61 @@ def cpu_baseline(w, budget_s=12.0):
                         f"extrapolated to the whole batch; 1 thread: {s1.size} tracks"))
 
 
+def residual_bench(args):
+    """Residual maps of the 450k batch (one map's worth of tracks): match and
+    refit on the GPU, clusters on 64 pad rows per track, then the voxel sums
+    and the per-voxel fit, timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_2003_03174_amd import binding as B
+    from paper_2003_03174_amd import synth
+
+    log("generating c5_distortion_450k and its TPC clusters")
+    w = synth.load_workload("c5_distortion_450k")
+    cl = synth.tpc_clusters(w, 6)
+    n, m_cl = w["n_tracks"], cl["n_clusters"]
+    dev = torch.device("cuda", 0)
+    rs = (cl["sector"].astype(np.int64) << 16) | cl["row"].astype(np.int64)
+    dc = dict(y=torch.from_numpy(cl["y"].astype(np.float32)).to(dev),
+              z=torch.from_numpy(cl["z"].astype(np.float32)).to(dev),
+              row_sec=torch.from_numpy(rs.astype(np.int32)).to(dev),
+              first=torch.from_numpy(cl["first"]).to(dev))
+    d = B.device_inputs(synth.to_device_layout(w), "fp32")
+    m = B.Matcher(w["params"], "fp32")
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+    mo = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    r = m.refit(mo, d["y"], d["z"], d["det_row"])
+    nx, ny, nz = B.VOXELS
+    sums = torch.zeros((18 * nx * ny * nz, 8), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    ts = []
+    for k in range(args.warmup + args.steps):
+        sums.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, dist = m.residual_map(r, dc, sums=sums)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            ts.append(e0.elapsed_time(e1))
+    ms = sum(ts) / len(ts)
+    dd = dist.cpu().numpy()
+    m.close()
+    # algorithmic bytes: clusters (y, z, row/sector: 12 B) + references (28 B) + sums
+    ab = m_cl * 12 + n * 28 + sums.numel() * 8 * 2
+    line = {"metric": "TPC clusters accumulated into residual maps per second", "value": m_cl / (ms * 1e-3),
+            "unit": "clusters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"c5_distortion_450k refitted tracks, {m_cl} clusters on 64 pad rows, "
+                                   f"{18 * nx * ny * nz} voxels", "step": "residual sums + voxel fit"},
+            "voxels_solved": int(np.isfinite(dd[:, 0]).sum()),
+            "roofline": {"bound": "hbm", "achieved": ab / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_residual_sums + k_voxel_solve", "alg_bytes_per_launch": ab}}
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args):
     """Poisson stream of frames served by continuous batching (float path,
     two slots) against static batching with the plain double kernel."""
@@ -269,6 +324,7 @@ def main():
                     help="one-lane-per-track match as a persistent grid")
     ap.add_argument("--autotune", action="store_true", help="pick block size and lanes per track first")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson frame stream)")
+    ap.add_argument("--residuals", action="store_true", help="residual-map benchmark on the 450k batch")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-pool", type=int, default=48)
@@ -286,6 +342,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     if args.serve:
         serve_bench(args)
+        return
+    if args.residuals:
+        residual_bench(args)
         return
 
     if args.calibrate_copy:
