@@ -72,7 +72,8 @@ extern "C" {
 #define TRD_CFG_FORCE_FALLBACK 2u /* test hook (TRD_PREC_FP32): every track takes the
                                      double-covariance re-run */
 #define TRD_CFG_INPUT_ORDER 8u    /* match the tracks in the caller's order; by default
-                                     the one-lane-per-track launch first sorts them by
+                                     the one-lane-per-track and the several-hypotheses
+                                     launches first sort them by
                                      (group, sector, z, y) of the seed so that neighbouring
                                      lanes read neighbouring cells (results are the same,
                                      bit for bit, and come back in input order) */

@@ -185,7 +185,7 @@ int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1); }
 // for it (several lanes per road, several hypotheses)
 bool ordered(const trd_config &c)
 {
-    return !(c.flags & TRD_CFG_INPUT_ORDER) && c.search_lanes <= 1 && c.n_hyp == 0;
+    return !(c.flags & TRD_CFG_INPUT_ORDER) && c.search_lanes <= 1;
 }
 int64_t row_scalar(const trd_config &c) { return c.precision == TRD_PREC_FP64 ? 8 : 4; }
 int64_t trk_bytes(const trd_config &c, int64_t n)
@@ -466,18 +466,17 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
         io.ev_end = ctx->ev[slot][1];
         ctx->ev_count++;
     }
-    if (ctx->cfg.n_hyp > 0) {
-        launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, s);
-        return launch_status();
-    }
     TrackOrder ord_buf{};
     if (ord) {
         ord_buf = TrackOrder{ctx->d_tkey_a, ctx->d_tkey_b, ctx->d_tval_a, ctx->d_tval_b, ctx->d_trank,
                              ctx->d_thist, ctx->d_thist_off, ctx->d_ttiles, ctx->d_rows_in, ctx->d_rows_out};
         launch_order_in(ctx->cfg.precision, io, ctx->n_groups, ord_buf, s);
     }
-    launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size, ctx->cfg.search_lanes,
-                 (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu, s);
+    if (ctx->cfg.n_hyp > 0)
+        launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, s);
+    else
+        launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size, ctx->cfg.search_lanes,
+                     (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu, s);
     if (ord) launch_order_out(ctx->cfg.precision, io, ord_buf, s);
     return launch_status();
 }

@@ -1266,12 +1266,13 @@ __device__ __forceinline__ bool beam_track(const DevCfg<TS> &g, const MatchIO &i
         }
     }
     if (h == 0) {
-        const int64_t n = io.n;
-        TS *ochl = reinterpret_cast<TS *>(io.ochi2l);
+        Acc<TS> lay;
+        acc_init(lay);
 #pragma unroll
         for (int k = 0; k < kLayers; k++) {
-            io.oidx[k * n + i] = H.idx[k];
-            if (ochl) ochl[k * n + i] = H.chi2l[k];
+            lay.lidx = H.idx[k];
+            lay.lchi = H.chi2l[k];
+            write_layer(io, i, k, lay);
         }
         Acc<TS> acc;
         acc.nmatch = H.nmatch;
@@ -1287,7 +1288,7 @@ template <typename TS, typename TC, int N, bool kFloatCov>
 __global__ void __launch_bounds__(256) k_match_beam(DevCfg<TS> g, MatchIO io)
 {
     const int lane = threadIdx.x & 63, h = lane & (N - 1), base = lane & ~(N - 1);
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / N;
+    const int64_t i = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / N;
     if (i >= io.n) return;  // uniform over the group
     if (!beam_track<TS, TC, N, kFloatCov>(g, io, i, h, base, 0u) && h == 0)
         io.fb_list[atomicAdd(io.fb_count, 1u)] = (int32_t)i;
