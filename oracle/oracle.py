@@ -18,6 +18,7 @@ _SRC = os.path.join(_HERE, "trd_oracle.c")
 _LIB = os.environ.get("TRD_ORACLE_LIB") or os.path.join(_HERE, "libtrd_oracle.so")
 
 ST_STOP_SNP, ST_ROT_FAIL, ST_OUT_OF_Z, ST_BAD_INPUT = 1, 2, 4, 32
+ST_STOPPED = 256
 FL_P1, FL_P2, FL_P3, FL_P4 = 1, 2, 4, 8
 
 
@@ -37,6 +38,8 @@ class OCfg(C.Structure):
         ("n_rows", C.c_int32), ("n_yb", C.c_int32), ("n_db", C.c_int32),
         ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
         ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32), ("pad_", C.c_int32),
+        ("eloss_xrho", C.c_double), ("eloss_za", C.c_double), ("eloss_i", C.c_double),
+        ("absent", C.c_uint8 * 540), ("pad2_", C.c_uint8 * 4),
     ]
 
 class OTpc(C.Structure):
@@ -85,7 +88,7 @@ def lib():
         L.oracle_bin.argtypes = [C.POINTER(OCfg), C.c_int64, dp, dp, dp, up, ip, C.c_int32, ip, up]
         L.oracle_match.argtypes = ([C.POINTER(OCfg), C.c_int64, dp, dp, dp, ip, ip,
                                     C.c_int64, dp, dp, dp, up, ip, C.c_int32, C.c_int32, C.c_int32,
-                                    ip, dp, dp, dp, ip, dp, dp, ip, up, up, ip, lp, dp, dp, dp, ip])
+                                    ip, dp, dp, dp, ip, dp, dp, ip, up, up, ip, lp, dp, dp, dp, ip, dp])
         L.oracle_refit.argtypes = [C.POINTER(OCfg), C.c_int64, dp, dp, ip, ip, C.c_int64, dp, dp, up,
                                    C.c_int32, dp, dp, dp, ip, dp, ip, up]
         L.oracle_residuals.argtypes = [C.POINTER(OCfg), C.POINTER(OTpc), C.c_int64, dp, dp, ip, up, lp, dp, dp,
@@ -94,6 +97,10 @@ def lib():
         L.oracle_propagate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
         L.oracle_rotate.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, dp]
         L.oracle_add_ms.argtypes = [C.POINTER(OCfg), dp, dp]
+        L.oracle_eloss.argtypes = [C.POINTER(OCfg), dp, dp, C.c_int]
+        L.oracle_bethe.argtypes = [C.POINTER(OCfg), C.c_double, C.c_double]
+        L.oracle_bethe.restype = C.c_double
+        L.oracle_chamber_at.argtypes = [C.POINTER(OCfg), C.c_int, C.c_int, C.c_double]
         L.oracle_update.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
         L.oracle_ldl_pd.argtypes = [dp]
         L.oracle_key.argtypes = [C.POINTER(OCfg), C.c_double, C.c_double, C.c_double, C.c_uint32,
@@ -129,6 +136,14 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
     for k in range(5):
         c.refit_cov[k] = float(P.get("refit_cov", REFIT_COV)[k])
     c.refit_min = int(P.get("refit_min", REFIT_MIN))
+    c.eloss_xrho = float(P.get("eloss_xrho", 0.0))
+    c.eloss_za = float(P.get("eloss_za", 0.5))
+    c.eloss_i = float(P.get("eloss_i", 1e-7))
+    ab = P.get("absent")
+    if ab is not None:
+        ab = np.asarray(ab).reshape(540)
+        for d in range(540):
+            c.absent[d] = 1 if ab[d] else 0
     return c
 
 
@@ -187,7 +202,7 @@ def match(params, w, *, mode="binned", threads=0, layers=False, margins=None, tr
         x=np.zeros(n), sector=np.zeros(n, np.int32), chi2=np.zeros(n),
         chi2_layer=np.zeros((6, n)), n_match=np.zeros(n, np.int32),
         status=np.zeros(n, np.uint32), flags=np.zeros(n, np.uint32),
-        flag_layer=np.zeros(n, np.int32), n_cand=np.zeros(n, np.int64),
+        flag_layer=np.zeros(n, np.int32), n_cand=np.zeros(n, np.int64), cost=np.zeros(n),
     )
     if layers:
         o.update(lp=np.zeros((6, 5, n)), lc=np.zeros((6, 15, n)), lx=np.zeros((6, n)),
@@ -201,7 +216,8 @@ def match(params, w, *, mode="binned", threads=0, layers=False, margins=None, tr
         _ptr(o["sector"], ip), _ptr(o["chi2"], dp), _ptr(o["chi2_layer"], dp),
         _ptr(o["n_match"], ip), _ptr(o["status"], up), _ptr(o["flags"], up),
         _ptr(o["flag_layer"], ip), _ptr(o["n_cand"], C.c_int64),
-        _ptr(o.get("lp"), dp), _ptr(o.get("lc"), dp), _ptr(o.get("lx"), dp), _ptr(o.get("lsec"), ip))
+        _ptr(o.get("lp"), dp), _ptr(o.get("lc"), dp), _ptr(o.get("lx"), dp), _ptr(o.get("lsec"), ip),
+        _ptr(o["cost"], dp))
     assert rc == 0, rc
     return o
 
@@ -308,6 +324,26 @@ def add_ms(params, p, cov):
     cv = _f64(cov).copy()
     L.oracle_add_ms(C.byref(cfg), _ptr(p, C.c_double), _ptr(cv, C.c_double))
     return cv
+
+
+def eloss(params, p, cov, direction=1):
+    """The layer's mean energy loss at the state p (direction +1 outward,
+    -1 inward).  Returns (ok, p, cov)."""
+    L = lib()
+    cfg = _cfg_only(params)
+    p = _f64(p).copy()
+    cv = _f64(cov).copy()
+    ok = L.oracle_eloss(C.byref(cfg), _ptr(p, C.c_double), _ptr(cv, C.c_double), int(direction))
+    return bool(ok), p, cv
+
+
+def bethe(params, p, m):
+    """Mean energy loss rate (GeV cm^2/g) of the oracle's material model."""
+    return float(lib().oracle_bethe(C.byref(_cfg_only(params)), float(p), float(m)))
+
+
+def chamber_at(params, sec, layer, z):
+    return int(lib().oracle_chamber_at(C.byref(_cfg_only(params)), int(sec), int(layer), float(z)))
 
 
 def update(p, cov, ry, rz, tau, vy, vz):

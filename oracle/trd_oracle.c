@@ -35,7 +35,12 @@
  *   - tracklet cells: key = (((group*540 + det)*n_db + dbin)*n_yb + ybin)*n_rows
  *     + row, ybin = clamp(floor((y - y_min) * (1/w)), 0, n_yb-1) and dbin the
  *     same on dy with its own width, both in double; a road is searched over
- *     the deflection bins x y bins x pad rows that overlap it.
+ *     the deflection bins x y bins x pad rows that overlap it;
+ *   - optional realistic detector model: after the scattering, the layer's
+ *     mean energy loss (Bethe formula) lowers the momentum; chamber slots
+ *     marked absent hold no tracklets (their tracklets are dropped), and in
+ *     the hypothesis mode a layer whose predicted point lies in an absent
+ *     chamber costs no penalty.
  *
  * Decision-margin flags mark tracks where a gate, tie or geometric decision
  * lies within a margin, so that a correct implementation in a different
@@ -61,6 +66,7 @@
 #define ST_BAD_INPUT 32u
 #define ST_REFIT_FEW 64u   /* refit: fewer tracklets than refit_min, copied */
 #define ST_REFIT_SKIP 128u /* refit: a tracklet more than one sector away was skipped */
+#define ST_STOPPED 256u    /* the layer's energy loss left no kinetic energy */
 /* decision-margin flags */
 #define FL_P1 1u /* winner near one of its gates */
 #define FL_P2 2u /* a loser fails exactly one gate by a margin and would win */
@@ -84,6 +90,13 @@ typedef struct {
     double chi2_penalty;        /* cost of a layer without a tracklet (hypothesis mode) */
     double refit_cov[5];        /* TRD-only refit: starting covariance (diagonal) */
     int32_t refit_min, pad_;    /* TRD-only refit: fewest tracklets refitted */
+    /* realistic detector model (Sect. 3: propagation with energy loss; the
+     * detector has 522 of its 540 chamber slots equipped) */
+    double eloss_xrho;          /* layer material crossed at normal incidence, g/cm^2 (0: no loss) */
+    double eloss_za;            /* its Z/A */
+    double eloss_i;             /* its mean excitation energy, GeV */
+    uint8_t absent[NDET];       /* nonzero: no chamber in this slot */
+    uint8_t pad2_[4];
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -258,6 +271,58 @@ static void add_ms(const double p[5], double C[5][5], const ocfg *g)
     C[4][3] = C[3][4];
 }
 
+/* Mean energy loss rate of a unit-charge particle of momentum p and mass m
+ * in the layer material: the Bethe formula without density-effect or shell
+ * corrections, with the kinematic maximum energy transfer to one electron;
+ * GeV cm^2/g, never below zero. */
+static double bethe(double p, double m, const ocfg *g)
+{
+    const double K = 0.307075e-3, me = 0.51099895e-3;
+    double E = sqrt(p * p + m * m);
+    double bg = p / m, gam = E / m, b2 = (p * p) / (E * E), r = me / m;
+    double tmax = 2.0 * me * bg * bg / (1.0 + 2.0 * gam * r + r * r);
+    double v = K * g->eloss_za / b2 * (0.5 * log(2.0 * me * bg * bg * tmax / (g->eloss_i * g->eloss_i)) - b2);
+    return v > 0.0 ? v : 0.0;
+}
+
+/* The layer's mean energy loss at the current point, along the path
+ * x_rho sqrt(1 + tan^2 lambda) / cos(phi).  Outward (dir = +1) the energy
+ * falls by it, inward (dir = -1) it is given back; the rate is taken at the
+ * momentum before the step.  q/pT scales by p/p'.  Its covariance row and
+ * column scale by d(q/pT')/d(q/pT) with the loss held fixed, (p/p')^3 E'/E,
+ * and the diagonal element by the square.  Returns 0 (state untouched) if
+ * the energy would not exceed the mass. */
+static int eloss(double p[5], double C[5][5], const ocfg *g, int dir)
+{
+    double s = p[2], t = p[3], c = p[4];
+    if (c == 0.0 || !(g->eloss_xrho > 0.0)) return 1;
+    double f = sqrt(1.0 - s * s), tt = 1.0 + t * t;
+    double pp = sqrt(tt) / fabs(c), m = g->mass;
+    double E = sqrt(pp * pp + m * m);
+    double dE = bethe(pp, m, g) * g->eloss_xrho * sqrt(tt) / f;
+    double E2 = dir > 0 ? E - dE : E + dE;
+    if (!(E2 > m)) return 0;
+    double p2 = sqrt(E2 * E2 - m * m);
+    double k = pp / p2;
+    double j = k * k * k * E2 / E;
+    p[4] = c * k;
+    for (int a = 0; a < 4; a++) {
+        C[4][a] *= j;
+        C[a][4] *= j;
+    }
+    C[4][4] *= j * j;
+    return 1;
+}
+
+/* Chamber slot holding the point (sector, z) of layer l: -1 outside the
+ * stacks in z. */
+static int chamber_at(const ocfg *g, int sec, int l, double z)
+{
+    double row = floor((z - g->z_min) / g->pad_len);
+    if (!(row >= 0.0) || row >= (double)(NSTK * g->n_rows)) return -1;
+    return sec * (NSTK * NLAY) + ((int)row / g->n_rows) * NLAY + l;
+}
+
 /* Kalman update with the measurement m = (y_tkl, z_tkl) of the model
  * h(p) = (y + tau (z - z_tkl), z); r = m - h(p).  Joseph form. */
 static void kalman_update(double p[5], double C[5][5], double ry, double rz,
@@ -363,7 +428,7 @@ static int64_t tkl_key(const ocfg *g, double y, double z, double dy, uint32_t de
 {
     uint32_t det = det_row >> 5, row = det_row & 31u;
     if (det >= NDET || (int32_t)row >= g->n_rows || grp < 0 || grp >= n_groups ||
-        !isfinite(y) || !isfinite(z) || !isfinite(dy))
+        !isfinite(y) || !isfinite(z) || !isfinite(dy) || g->absent[det])
         return n_cells_of(g, n_groups);
     return ((((int64_t)grp * NDET + det) * g->n_db + dbin_of(g, dy)) * g->n_yb + ybin_of(g, y)) *
                g->n_rows + row;
@@ -430,6 +495,7 @@ typedef struct {
     int64_t *n_cand;       /* optional: candidates looked at */
     double *lp, *lc, *lx;  /* optional per-layer state: [6][5][n], [6][15][n], [6][n] */
     int32_t *lsec;         /* optional [6][n] */
+    double *cost;          /* optional [n]: cost of the answer (hypothesis mode; NaN otherwise) */
 } oout;
 
 /* prediction-side quantities of one layer's road */
@@ -487,7 +553,7 @@ static void gather_candidates(const ocfg *g, const otkl *T, const road_t *r, int
         for (int64_t j = 0; j < T->n; j++) {
             uint32_t det = T->det_row[j] >> 5, row = T->det_row[j] & 31u;
             int32_t gj = T->grp ? T->grp[j] : 0;
-            if (det >= NDET || (int32_t)row >= g->n_rows || gj != grp) continue;
+            if (det >= NDET || (int32_t)row >= g->n_rows || gj != grp || g->absent[det]) continue;
             if (!isfinite(T->y[j]) || !isfinite(T->z[j]) || !isfinite(T->dy[j])) continue;
             if ((int)(det / (NSTK * NLAY)) != sec || (int)(det % NLAY) != l) continue;
             ilist_push(L, j);
@@ -514,6 +580,7 @@ static void gather_candidates(const ocfg *g, const otkl *T, const road_t *r, int
         if (r0 < 0) r0 = 0;
         if (r1 > g->n_rows - 1) r1 = g->n_rows - 1;
         int det = sec * (NSTK * NLAY) + stack * NLAY + l;
+        if (g->absent[det]) continue;
         for (int db = db0; db <= db1; db++)
             for (int yb = yb0; yb <= yb1; yb++) {
                 int64_t base = ((((int64_t)grp * NDET + det) * g->n_db + db) * g->n_yb + yb) * g->n_rows;
@@ -574,12 +641,18 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
             sec = (sec + (up ? 1 : NSEC - 1)) % NSEC;
             if (!propagate(p, C, &x, xl, g, &lf, NULL)) { status |= ST_STOP_SNP; stop = 1; break; }
         }
+        if (!stop) {
+            add_ms(p, C, g);
+            if (!eloss(p, C, g, 1)) {
+                status |= ST_STOPPED;
+                stop = 1;
+            }
+        }
         if (stop) {
             flags |= lf;
             if (lf && flag_layer == NLAY) flag_layer = l;
             break;
         }
-        add_ms(p, C, g);
 
         /* road from the covariance */
         road_t r;
@@ -695,6 +768,7 @@ done:
     o->flags[i] = flags;
     if (o->flag_layer) o->flag_layer[i] = flag_layer;
     if (o->n_cand) o->n_cand[i] = ncand;
+    if (o->cost) o->cost[i] = NAN;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -778,6 +852,10 @@ static int hyp_predict(const ocfg *g, hyp_t *h, int l, unsigned *lf)
         if (!propagate(h->p, h->C, &h->x, xl, g, lf, NULL)) { h->status |= ST_STOP_SNP; return 0; }
     }
     add_ms(h->p, h->C, g);
+    if (!eloss(h->p, h->C, g, 1)) {
+        h->status |= ST_STOPPED;
+        return 0;
+    }
     return 1;
 }
 
@@ -872,7 +950,17 @@ static void match_one_beam(const ocfg *g, int64_t i, int64_t n, const double *ip
                     }
                 }
             }
-            clist_push(K, Hh->cost + g->chi2_penalty, 0.0, h, -1);
+            /* no chamber in this slot: nothing to miss, no penalty */
+            double pen = g->chi2_penalty;
+            if (Hh->live) {
+                double mzs = g->m_rel * fabs(Hh->p[1]) + g->m_len;
+                int d0 = chamber_at(g, Hh->sec, l, Hh->p[1]);
+                int dlo = chamber_at(g, Hh->sec, l, Hh->p[1] - mzs), dhi = chamber_at(g, Hh->sec, l, Hh->p[1] + mzs);
+                int a0 = d0 >= 0 && g->absent[d0], alo = dlo >= 0 && g->absent[dlo], ahi = dhi >= 0 && g->absent[dhi];
+                if (a0 != alo || a0 != ahi) flags |= FL_P4;
+                if (a0) pen = 0.0;
+            }
+            clist_push(K, Hh->cost + pen, 0.0, h, -1);
         }
         qsort(K->v, (size_t)K->n, sizeof(child_t), cmp_child);
         int nk = K->n < N ? (int)K->n : N;
@@ -936,6 +1024,7 @@ done:
         /* the answer depends on every layer's selection */
         if (o->flag_layer) o->flag_layer[i] = flags ? 0 : NLAY;
         if (o->n_cand) o->n_cand[i] = ncand;
+        if (o->cost) o->cost[i] = b->cost;
     }
 }
 
@@ -949,7 +1038,7 @@ int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *t
                  int32_t *idx, double *op, double *oc, double *ox, int32_t *osec,
                  double *ochi2, double *ochi2_layer, int32_t *on_match, uint32_t *ostatus,
                  uint32_t *oflags, int32_t *oflag_layer, int64_t *on_cand,
-                 double *lp, double *lc, double *lx, int32_t *lsec)
+                 double *lp, double *lc, double *lx, int32_t *lsec, double *ocost)
 {
     otkl T = {ky, kz, kdy, kdetrow, kgrp, n_tkl, NULL, NULL, n_groups, mode == 1};
     int32_t *perm = NULL;
@@ -967,7 +1056,7 @@ int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *t
     double dxmax = 0.0;
     for (int d = 0; d < NDET; d++) dxmax = fabs(g->dx_chamber[d]) > dxmax ? fabs(g->dx_chamber[d]) : dxmax;
     oout o = {idx, op, oc, ox, osec, ochi2, ochi2_layer, on_match, ostatus, oflags, oflag_layer,
-              on_cand, lp, lc, lx, lsec};
+              on_cand, lp, lc, lx, lsec, ocost};
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
@@ -1080,7 +1169,10 @@ static void refit_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
                     if (!(fabs(p[2]) < g->snp_max)) { status |= ST_STOP_SNP; break; }
                 }
             }
-            if (l > 0) add_ms(p, C, g);
+            if (l > 0) {
+                add_ms(p, C, g);
+                eloss(p, C, g, -1);
+            }
         }
     }
     double pk[15];
@@ -1252,6 +1344,19 @@ void oracle_add_ms(const ocfg *g, const double *p, double *cpk)
     add_ms(p, C, g);
     pack(C, cpk);
 }
+
+int oracle_eloss(const ocfg *g, double *p, double *cpk, int dir)
+{
+    double C[5][5];
+    unpack(cpk, C);
+    int ok = eloss(p, C, g, dir);
+    pack(C, cpk);
+    return ok;
+}
+
+double oracle_bethe(const ocfg *g, double p, double m) { return bethe(p, m, g); }
+
+int oracle_chamber_at(const ocfg *g, int sec, int l, double z) { return chamber_at(g, sec, l, z); }
 
 void oracle_update(double *p, double *cpk, double ry, double rz, double tau, double vy, double vz)
 {

@@ -64,13 +64,41 @@ def default_params(**over):
         n_sigma_dy=4.0,
         n_sigma_road=math.sqrt(chi2_max),
         snp_max=0.95,
+        # realistic detector model, off by default: mean energy loss in each
+        # layer's material (g/cm^2 at normal incidence, Z/A, mean excitation
+        # energy in GeV) and the chamber slots without a chamber
+        eloss_xrho=0.0,
+        eloss_za=0.5,
+        eloss_i=1e-7,
+        absent=np.zeros(N_DET, dtype=np.uint8),
     )
     for k, v in over.items():
         if k not in p:
             raise KeyError(f"unknown parameter {k!r}")
         p[k] = v
     p["dx_chamber"] = np.asarray(p["dx_chamber"], dtype=np.float64).reshape(N_DET)
+    p["absent"] = (np.asarray(p["absent"]).reshape(N_DET) != 0).astype(np.uint8)
     return p
+
+
+def absent_522():
+    """The installed detector: 522 of the 540 chamber slots, the middle stack
+    of sectors 13, 14 and 15 (in front of the photon spectrometer) left
+    empty."""
+    a = np.zeros(N_DET, dtype=np.uint8)
+    for sec in (13, 14, 15):
+        for l in range(N_LAYERS):
+            a[sec * N_STACKS * N_LAYERS + 2 * N_LAYERS + l] = 1
+    return a
+
+
+def realistic_params(**over):
+    """Detector model with energy loss and the 522-chamber layout.  The layer
+    material is a plastic-like radiator and chamber: 1.2 g/cm^2 (about
+    X/X0 = 0.03 at X0 = 40 g/cm^2), Z/A = 0.53, I = 70 eV."""
+    p = dict(eloss_xrho=1.2, eloss_za=0.53, eloss_i=70e-9, absent=absent_522())
+    p.update(over)
+    return default_params(**p)
 
 
 def tilt_pm2deg():
@@ -151,6 +179,20 @@ def _cross_plane(X, Y, Phi, cu, alpha, xl, dt):
     arc = chord * asin_over_h * np.sign(xl - x0)
     Phi1 = alpha + np.arctan2(snp, csp)
     return ok, y, snp, csp, X1, Y1, arc, Phi1
+
+
+def bethe_rate(p, mass, za, i_exc):
+    """Mean energy-loss rate (GeV cm^2/g) of a unit-charge particle: the Bethe
+    formula without density-effect or shell terms (PDG review of the passage
+    of particles through matter), clipped at zero."""
+    me = 0.51099895e-3
+    e = np.sqrt(p * p + mass * mass)
+    bg2 = (p / mass) ** 2
+    b2 = bg2 / (1.0 + bg2)
+    gam = e / mass
+    wmax = 2.0 * me * bg2 / (1.0 + 2.0 * gam * me / mass + (me / mass) ** 2)
+    v = 0.307075e-3 * za / b2 * (0.5 * np.log(2.0 * me * bg2 * wmax / (i_exc * i_exc)) - b2)
+    return np.maximum(v, 0.0)
 
 
 def highland_theta0(p, beta, xi):
@@ -279,6 +321,19 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
             c = np.where(alive, np.sign(c) / (pabs * np.cos(lam2)), c)
             phl = Phi - a
             alive = alive & (np.cos(phl) > 0) & (np.abs(np.sin(phl)) < P["snp_max"])
+        # mean energy loss in the layer: the path through the slab is its
+        # thickness over the cosine of the angle to the slab normal (the
+        # sector's x axis)
+        if P["eloss_xrho"] > 0:
+            m = dt(P["mass"])
+            cos_inc = np.cos(np.arctan(tg)) * np.cos(Phi - a)
+            cos_inc = np.where(alive & (cos_inc > 0), cos_inc, dt(1.0))
+            e0 = np.sqrt(pabs * pabs + m * m)
+            e1 = e0 - bethe_rate(pabs, m, P["eloss_za"], P["eloss_i"]) * dt(P["eloss_xrho"]) / cos_inc
+            alive = alive & (e1 > m)
+            p1 = np.sqrt(np.maximum(e1 * e1 - m * m, dt(0.0)))
+            c = np.where(alive, c * (pabs / np.where(alive, p1, pabs)), c)
+            pabs = np.where(alive, p1, pabs)
         phl = Phi - a
         truth["sec"][l] = np.where(alive, sec, -1)
         truth["x"][l] = np.where(alive, np.float64(xl), np.nan)
@@ -344,7 +399,7 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
         if tr is None:
             continue
         ids, ym, zm, dym, det, row, _ = tr
-        keep = ~drop[l, ids]
+        keep = ~drop[l, ids] & (P["absent"][det] == 0)
         ys.append(ym[keep]); zs.append(zm[keep]); dys.append(dym[keep])
         dets.append(det[keep]); rows.append(row[keep]); labels.append(ids[keep])
         lays.append(np.full(int(keep.sum()), l))
@@ -356,13 +411,17 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
         flay = rng.integers(0, N_LAYERS, n_fake)
         frow = rng.integers(0, P["n_rows"], n_fake)
         fxl = np.asarray(P["x_layer"])[flay]
-        ys.append(rng.uniform(-1.0, 1.0, n_fake) * fxl * tan10)
-        zs.append(zmin + (fst * P["n_rows"] + frow + 0.5) * pad)
-        dys.append(rng.uniform(-1.0, 1.0, n_fake))
-        dets.append(fsec * (N_STACKS * N_LAYERS) + fst * N_LAYERS + flay)
-        rows.append(frow)
-        labels.append(np.full(n_fake, -1))
-        lays.append(flay)
+        fy = rng.uniform(-1.0, 1.0, n_fake) * fxl * tan10
+        fdy = rng.uniform(-1.0, 1.0, n_fake)
+        fdet = fsec * (N_STACKS * N_LAYERS) + fst * N_LAYERS + flay
+        fk = P["absent"][fdet] == 0
+        ys.append(fy[fk])
+        zs.append((zmin + (fst * P["n_rows"] + frow + 0.5) * pad)[fk])
+        dys.append(fdy[fk])
+        dets.append(fdet[fk])
+        rows.append(frow[fk])
+        labels.append(np.full(int(fk.sum()), -1))
+        lays.append(flay[fk])
     ty = np.concatenate(ys) if ys else np.zeros(0)
     tz = np.concatenate(zs) if zs else np.zeros(0)
     tdy = np.concatenate(dys) if dys else np.zeros(0)

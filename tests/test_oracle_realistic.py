@@ -1,0 +1,303 @@
+"""Pins of the oracle's realistic detector model: the mean energy loss in each
+layer (Sect. 3: the extrapolation to a chamber accounts for energy loss) and
+the chamber slots without a chamber (the detector has 522 of 540).
+
+The loss rate is pinned to published minimum-ionization values, its
+kinematics and covariance scaling to finite differences, its placement and
+path length to the generator's independent simulation of the same physics
+(noise-free chi2 and truth agreement), the chamber mask to brute force and to
+the generator's geometry, and the hypothesis penalty rule to the costs it
+implies on noise-free tracks.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2003_03174_amd import synth
+
+MU = 0.1056583755  # muon mass, GeV
+
+# Minimum mean energy-loss rates of gases (MeV cm^2/g) with their Z/A and
+# mean excitation energies (eV), from the Particle Data Group's tables of
+# atomic and nuclear properties of materials.  For gases the density effect
+# is negligible at minimum ionization, so the plain Bethe formula must
+# reproduce them.
+PDG_GAS_MIN = [
+    ("H2", 0.99212, 19.2, 4.103),
+    ("He", 0.49967, 41.8, 1.937),
+    ("N2", 0.49976, 82.0, 1.825),
+    ("Ar", 0.45059, 188.0, 1.519),
+    ("Xe", 0.41129, 482.0, 1.255),
+]
+
+COV0 = np.array([0.04, 0.001, 0.3, 1e-4, 2e-5, 0.05, 0.002, 1e-4, 3e-5,
+                 1e-4, 1e-6, 2e-6, 1e-4, 1e-6, 4e-4])
+
+
+def _params(**over):
+    return synth.realistic_params(**over)
+
+
+@pytest.mark.parametrize("gas", PDG_GAS_MIN, ids=[g[0] for g in PDG_GAS_MIN])
+def test_bethe_minimum_matches_published_gas_values(gas):
+    name, za, i_ev, ref = gas
+    P = _params(eloss_za=za, eloss_i=i_ev * 1e-9)
+    bg = np.logspace(0.0, 1.2, 600)
+    v = np.array([O.bethe(P, b * MU, MU) for b in bg]) * 1e3
+    k = int(np.argmin(v))
+    assert 2.5 < bg[k] < 4.0, bg[k]
+    assert abs(v[k] / ref - 1.0) < 2e-3, (name, v[k], ref)
+
+
+def test_bethe_rises_as_one_over_beta_squared_at_low_momentum():
+    """Far below minimum ionization the rate falls roughly as 1/beta^2: from
+    beta gamma = 0.3 to 0.6 it drops by more than a factor 2.5."""
+    P = _params()
+    r = O.bethe(P, 0.3 * MU, MU) / O.bethe(P, 0.6 * MU, MU)
+    assert 2.5 < r < 4.0, r
+
+
+def _state(s=0.2, t=0.5, c=1.0 / 0.4):
+    return np.array([3.0, -20.0, s, t, c])
+
+
+def test_eloss_changes_only_the_momentum():
+    P = _params()
+    p = _state()
+    ok, p2, c2 = O.eloss(P, p, COV0, 1)
+    assert ok
+    assert np.array_equal(p2[:4], p[:4])
+    assert np.sign(p2[4]) == np.sign(p[4]) and abs(p2[4]) > abs(p[4])
+    # covariance: only the q/pT row and column change
+    i44 = 14
+    qrow = {4, 8, 11, 13, 14}
+    for k in range(15):
+        if k not in qrow:
+            assert c2[k] == COV0[k]
+    j = c2[13] / COV0[13]
+    for k in (4, 8, 11):
+        assert math.isclose(c2[k] / COV0[k], j, rel_tol=1e-13)
+    assert math.isclose(c2[i44] / COV0[i44], j * j, rel_tol=1e-13)
+
+
+def _energy(c, t, m):
+    p = math.sqrt(1.0 + t * t) / abs(c)
+    return math.sqrt(p * p + m * m), p
+
+
+def test_eloss_energy_and_path_length():
+    """The energy drops by rate x thickness x path factor, the path factor being
+    1 / cos of the angle between the track and the slab normal."""
+    P = _params()
+    m = P["mass"]
+    for s, t in ((0.0, 0.0), (0.3, 0.0), (0.0, 0.8), (-0.5, -0.6)):
+        p = _state(s=s, t=t, c=-1.0 / 0.35)
+        ok, p2, _ = O.eloss(P, p, COV0, 1)
+        e1, pp = _energy(p[4], t, m)
+        e2, _ = _energy(p2[4], t, m)
+        cos_inc = math.cos(math.atan(t)) * math.cos(math.asin(s))
+        want = O.bethe(P, pp, m) * P["eloss_xrho"] / cos_inc
+        assert math.isclose(e1 - e2, want, rel_tol=1e-10), (s, t)
+
+
+def test_eloss_inward_undoes_outward_to_second_order():
+    P = _params()
+    p = _state(c=1.0 / 0.3)
+    _, p2, _ = O.eloss(P, p, COV0, 1)
+    _, p3, _ = O.eloss(P, p2, COV0, -1)
+    rel1 = abs(p2[4] / p[4] - 1.0)
+    assert 1e-4 < rel1 < 0.1
+    assert abs(p3[4] / p[4] - 1.0) < 5.0 * rel1 * rel1
+
+
+def test_eloss_jacobian_at_fixed_loss_finite_difference():
+    """d(q/pT')/d(q/pT) with the energy loss held at its value: the map
+    c -> c p(c) / sqrt((E(c) - dE)^2 - m^2) differentiated numerically."""
+    P = _params()
+    m = P["mass"]
+    for c0, t in ((1.0 / 0.35, 0.2), (-1.0 / 1.5, -0.7), (1.0 / 5.0, 0.0)):
+        p = _state(t=t, c=c0)
+        _, p2, c2 = O.eloss(P, p, COV0, 1)
+        e1, _ = _energy(c0, t, m)
+        e2, _ = _energy(p2[4], t, m)
+        de = e1 - e2
+
+        def cmap(c):
+            e, pp = _energy(c, t, m)
+            return c * pp / math.sqrt((e - de) ** 2 - m * m)
+
+        h = abs(c0) * 1e-6
+        fd = (cmap(c0 + h) - cmap(c0 - h)) / (2 * h)
+        assert math.isclose(cmap(c0), p2[4], rel_tol=1e-12)
+        assert math.isclose(c2[14] / COV0[14], fd * fd, rel_tol=1e-7), (c0, t)
+
+
+def test_eloss_stops_a_track_that_runs_out_of_energy():
+    P = _params(eloss_xrho=500.0)
+    p = _state(c=1.0 / 0.3)
+    ok, p2, c2 = O.eloss(P, p, COV0, 1)
+    assert not ok
+    assert np.array_equal(p2, p) and np.array_equal(c2, COV0)
+    # in the matcher: the layer-0 loss stops every slow track
+    w = synth.generate(n_tracks=200, seed=5, params=dict(eloss_xrho=60.0, eloss_za=0.53, eloss_i=70e-9),
+                       fake_ratio=0.0)
+    o = O.match(w["params"], w, threads=2)
+    assert np.any(o["status"] & O.ST_STOPPED)
+    stopped = (o["status"] & O.ST_STOPPED) != 0
+    assert np.all(o["n_match"][stopped] < 6)
+
+
+def _noise_free(params, n=300, seed=12, fake_ratio=0.5, ineff=0.0):
+    rng = np.random.default_rng(seed)
+    g = synth.generate_group(rng, params, n, noise_free=True, fake_ratio=fake_ratio, fp32=False,
+                             ineff_frac=ineff)
+    return synth._concat_groups([g], params)
+
+
+def test_noise_free_chi2_vanishes_with_energy_loss():
+    """The generator simulates the loss on its own; the oracle's prediction
+    lands exactly on every true tracklet."""
+    P = _params(absent=np.zeros(540))
+    w = _noise_free(P)
+    o = O.match(P, w, threads=2)
+    m = o["idx"] >= 0
+    assert m.sum() > 1500
+    assert np.all(o["idx"][m] == w["true_idx"][m])
+    assert o["chi2_layer"][m].max() < 1e-18
+    # without the loss in the oracle the same tracks miss by far more
+    Q = dict(P)
+    Q["eloss_xrho"] = 0.0
+    o2 = O.match(Q, w, threads=2)
+    m2 = (o2["idx"] >= 0) & (o2["idx"] == w["true_idx"])
+    assert o2["chi2_layer"][m2].max() > 1e-6
+
+
+def test_truth_momentum_through_the_layers():
+    P = _params(absent=np.zeros(540))
+    w = _noise_free(P, n=200, seed=3, fake_ratio=0.0)
+    o = O.match(P, w, threads=2, layers=True)
+    T = w["truth"]
+    for l in range(6):
+        ok = (o["idx"][l] >= 0) & (T["sec"][l] >= 0)
+        assert ok.sum() > 100
+        # after the update at layer l: the state on the post-loss truth
+        rel = np.abs(o["lp"][l, 4, ok] / T["qpt"][l, ok] - 1.0)
+        assert rel.max() < 1e-9, (l, rel.max())
+    # the momentum really fell: |q/pT| at layer 5 above the seed's
+    ok = T["sec"][5] >= 0
+    assert np.all(np.abs(T["qpt"][5, ok]) > np.abs(w["truth_seed"][4, ok]))
+
+
+def test_pulls_unit_width_with_energy_loss():
+    params = dict(chi2_max=1e9, n_sigma_road=40.0, eloss_xrho=1.2, eloss_za=0.53, eloss_i=70e-9)
+    w = synth.generate(n_tracks=5000, seed=43, fake_ratio=0.0, params=params)
+    o = O.match(w["params"], w, threads=4, layers=True)
+    T = w["truth"]
+    l = 5
+    ok = (o["lsec"][l] == T["sec"][l]) & (o["idx"][l] == w["true_idx"][l]) & (w["true_idx"][l] >= 0)
+    ok &= o["status"] == 0
+    N = ok.sum()
+    assert N > 3000
+    pull = (o["lp"][l, 4, ok] - T["qpt"][l, ok]) / np.sqrt(o["lc"][l, 14, ok])
+    assert abs(pull.mean()) < 4.0 / math.sqrt(N), pull.mean()
+    assert abs(pull.std() - 1.0) < 0.05, pull.std()
+
+
+def test_absent_chambers_hold_no_tracklets():
+    P = _params()
+    w = synth.generate(n_tracks=3000, seed=7, params=dict(absent=synth.absent_522()), fake_ratio=0.5)
+    assert synth.absent_522().sum() == 18
+    assert not np.any(P["absent"][w["tkl_det"]])
+    # tracklets planted there are dropped by the binning, like invalid ones
+    w2 = dict(w)
+    bad = np.nonzero(P["absent"])[0]
+    extra = np.random.default_rng(1).choice(bad, 50)
+    for k, v in (("tkl_y", np.zeros(50)), ("tkl_z", np.zeros(50)), ("tkl_dy", np.zeros(50)),
+                 ("tkl_det_row", (extra << 5).astype(np.uint32)), ("tkl_group", np.zeros(50, np.int32))):
+        w2[k] = np.concatenate([np.asarray(w[k]), v.astype(np.asarray(w[k]).dtype)])
+    perm, off = O.bin_tracklets(P, w2)
+    assert off[-1] == w["tkl_y"].size
+    assert not np.any(perm[: off[-1]] >= w["tkl_y"].size)
+
+
+def test_binned_equals_brute_force_with_absent_chambers():
+    params = dict(absent=synth.absent_522(), eloss_xrho=1.2, eloss_za=0.53, eloss_i=70e-9)
+    w = synth.generate(n_tracks=1500, seed=8, params=params, fake_ratio=0.5)
+    # plant tracklets in the absent slots: both searches must ignore them
+    rng = np.random.default_rng(2)
+    bad = np.nonzero(w["params"]["absent"])[0]
+    extra = rng.choice(bad, 400)
+    n0 = w["tkl_y"].size
+    w["tkl_y"] = np.concatenate([w["tkl_y"], rng.uniform(-40, 40, 400)])
+    w["tkl_z"] = np.concatenate([w["tkl_z"], rng.uniform(-60, 60, 400)])
+    w["tkl_dy"] = np.concatenate([w["tkl_dy"], rng.uniform(-1, 1, 400)])
+    w["tkl_det_row"] = np.concatenate([w["tkl_det_row"], (extra << 5 | rng.integers(0, 18, 400)).astype(np.uint32)])
+    w["tkl_group"] = np.concatenate([w["tkl_group"], np.zeros(400, np.int32)])
+    a = O.match(w["params"], w, threads=2)
+    b = O.match(w["params"], w, mode="brute", threads=2)
+    assert np.array_equal(a["idx"], b["idx"])
+    assert np.array_equal(a["p"], b["p"])
+    assert not np.any(a["idx"] >= n0)
+
+
+def test_chamber_slot_matches_the_generator_geometry():
+    P = synth.default_params()
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        sec, l = int(rng.integers(0, 18)), int(rng.integers(0, 6))
+        z = float(rng.uniform(-380.0, 380.0))
+        row = math.floor((z - P["z_min"]) / P["pad_len"])
+        want = -1 if not (0 <= row < 5 * P["n_rows"]) else sec * 30 + (row // P["n_rows"]) * 6 + l
+        assert O.chamber_at(P, sec, l, z) == want
+
+
+@pytest.mark.parametrize("n_hyp", [1, 2])
+def test_no_penalty_for_a_layer_without_a_chamber(n_hyp):
+    """Noise-free tracks: every layer crossed through an installed chamber
+    without a tracklet costs the penalty, a layer in an absent chamber costs
+    nothing, tracklets cost chi2 ~ 0."""
+    pen = 3.0
+    P = _params(eloss_xrho=0.0)
+    P.update(n_hyp=n_hyp, chi2_penalty=pen)
+    # a wide absent region so that many tracks cross it: the middle stack everywhere
+    ab = np.zeros(540, np.uint8)
+    for sec in range(18):
+        for l in range(6):
+            ab[sec * 30 + 2 * 6 + l] = 1
+    P["absent"] = ab
+    w = _noise_free(P, n=400, seed=21, fake_ratio=0.0, ineff=0.3)
+    o = O.match(P, w, threads=2)
+    T = w["truth"]
+    want = np.zeros(w["n_tracks"])
+    crossed_absent = np.zeros(w["n_tracks"], bool)
+    for l in range(6):
+        alive = T["sec"][l] >= 0
+        det = np.array([O.chamber_at(P, int(s), l, float(z)) if a else -1
+                        for s, z, a in zip(T["sec"][l], np.nan_to_num(T["z"][l]), alive)])
+        in_absent = alive & (det >= 0) & (ab[np.maximum(det, 0)] == 1)
+        crossed_absent |= in_absent
+        want += np.where((o["idx"][l] < 0) & ~in_absent, pen, 0.0)
+    ok = (o["status"] == 0) & (o["flags"] == 0)
+    assert crossed_absent[ok].sum() > 50
+    assert np.allclose(o["cost"][ok], want[ok] + o["chi2"][ok], rtol=0, atol=1e-9)
+    assert o["chi2"][ok].max() < 1e-12
+
+
+def test_refit_gives_back_the_energy_inward():
+    """TRD-only refit of noise-free tracks through layers with energy loss: the
+    inward pass restores the energy lost outward, so the exact tracklets fit
+    with chi2 ~ 0; a refit that ignored the loss would miss them."""
+    P = _params(absent=np.zeros(540))
+    P["refit_cov"] = (1.0, 100.0, 1e-2, 1e-2, 1.0)
+    w = _noise_free(P, n=300, seed=17, fake_ratio=0.0)
+    o = O.match(P, w, threads=2)
+    r = O.refit(P, o, o["idx"], w, threads=2)
+    ok = (r["status"] == 0) & (r["n_used"] == 6)
+    assert ok.sum() > 150
+    assert r["chi2"][ok].max() < 1e-6, r["chi2"][ok].max()
+    Q = dict(P)
+    Q["eloss_xrho"] = 0.0
+    r2 = O.refit(Q, o, o["idx"], w, threads=2)
+    assert np.median(r2["chi2"][ok]) > 1e-4
