@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick block size and lanes per track first")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson frame stream)")
     ap.add_argument("--residuals", action="store_true", help="residual-map benchmark on the 450k batch")
+    ap.add_argument("--realistic", action="store_true",
+                    help="realistic detector: energy loss in every layer and the 522-chamber layout")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-pool", type=int, default=48)
@@ -357,7 +359,10 @@ def main():
         log("calibration: 3 x (512 MiB read + 512 MiB written) by an elementwise add")
         del src, dst
     log(f"generating {args.workload}")
-    w = synth.load_workload(args.workload)
+    if args.realistic:
+        w = synth.generate(args.workload, params=synth.realistic_overrides())
+    else:
+        w = synth.load_workload(args.workload)
     if args.n_hyp:
         w = dict(w)
         w["params"] = dict(w["params"], n_hyp=args.n_hyp,
@@ -388,7 +393,7 @@ def main():
     achieved = ab / (kernel_avg * 1e-3) / 1e9
     traffic = profiled_traffic() if (args.workload == "c5_distortion_450k" and args.precision == "fp32"
                                      and not args.search_lanes > 1 and not args.persistent
-                                     and not args.n_hyp) else None
+                                     and not args.n_hyp and not args.realistic) else None
     line = {
         "metric": "matched tracks/s (6-layer Kalman)",
         "value": n / (ms * 1e-3),
@@ -404,7 +409,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {n} seed tracks, {ntk} tracklets, {ng} group(s); "
-                        + synth.describe(args.workload) + f"; {n_cells} cells",
+                        + synth.describe(args.workload) + f"; {n_cells} cells"
+                        + ("; realistic detector: Bethe energy loss of 1.2 g/cm^2 per layer, "
+                           "522 of 540 chambers" if args.realistic else ""),
             "graph": bool(args.graph),
             "precision": args.precision,
             "block_size": args.block_size or 256,

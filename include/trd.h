@@ -66,6 +66,7 @@ extern "C" {
                                     or covariance not positive definite; copied through */
 #define TRD_TRK_REFIT_FEW 64u    /* trd_refit: fewer than refit_min tracklets; copied */
 #define TRD_TRK_REFIT_SKIP 128u  /* trd_refit: a tracklet more than one sector away was skipped */
+#define TRD_TRK_STOPPED 256u     /* a layer's energy loss left the particle no kinetic energy */
 
 /* config flags */
 #define TRD_CFG_FAIL_ALLOC 1u     /* test hook: trd_create fails with TRD_ENOMEM */
@@ -140,6 +141,22 @@ typedef struct trd_config {
     int32_t vox_nx, vox_ny, vox_nz; /* voxels per sector in x, y/x (over +-tan 10 deg),
                                  z/x (over +-1); 18 * nx * ny * nz <= 2048 */
     int32_t vox_min;          /* fewest clusters for a voxel's distortion vector */
+    /* Realistic detector model (Sect. 3: the extrapolation to a chamber
+       accounts for energy loss; the detector equips 522 of its 540 slots). */
+    double eloss_xrho;        /* material of one layer crossed at normal incidence, g/cm^2;
+                                 0 = no energy loss.  After each layer's scattering the mean
+                                 loss (Bethe formula without density or shell terms, rate at
+                                 the momentum before the loss) times the path through the
+                                 slab lowers the energy (matching) or restores it (trd_refit,
+                                 inward); q/pT scales by p/p' and its covariance row by
+                                 (p/p')^3 E'/E.  A particle left with E <= m stops
+                                 (TRD_TRK_STOPPED). */
+    double eloss_za;          /* Z/A of that material (> 0 when eloss_xrho > 0) */
+    double eloss_i;           /* its mean excitation energy, GeV (> 0 when eloss_xrho > 0) */
+    uint8_t chamber_absent[540]; /* nonzero: no chamber in this slot (sector * 30 + stack * 6
+                                 + layer).  Its tracklets are dropped at load; with n_hyp >= 1
+                                 a layer whose predicted point lies in such a slot costs no
+                                 chi2_penalty. */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */

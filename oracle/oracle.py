@@ -39,7 +39,7 @@ class OCfg(C.Structure):
         ("n_hyp", C.c_int32), ("chi2_penalty", C.c_double),
         ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32), ("pad_", C.c_int32),
         ("eloss_xrho", C.c_double), ("eloss_za", C.c_double), ("eloss_i", C.c_double),
-        ("absent", C.c_uint8 * 540), ("pad2_", C.c_uint8 * 4),
+        ("absent", C.c_uint8 * 540), ("pad2_", C.c_uint8 * 4), ("m_ke", C.c_double),
     ]
 
 class OTpc(C.Structure):
@@ -111,7 +111,7 @@ def lib():
     return _lib
 
 
-def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0):
+def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0, m_ke=1e-3):
     c = OCfg()
     P = params
     for l in range(6):
@@ -130,6 +130,7 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
     c.chi2_max, c.n_sigma_dy = P["chi2_max"], P["n_sigma_dy"]
     c.n_sigma_road, c.snp_max = P["n_sigma_road"], P["snp_max"]
     c.m_rel, c.m_len, c.m_dy, c.m_chi2, c.m_snp = margin_rel, m_len, m_dy, m_chi2, m_snp
+    c.m_ke = m_ke
     c.n_rows, c.n_yb = P["n_rows"], P["n_yb"]
     c.n_hyp = int(P.get("n_hyp", 0))
     c.chi2_penalty = float(P.get("chi2_penalty", P["chi2_max"]))

@@ -97,6 +97,8 @@ typedef struct {
     double eloss_i;             /* its mean excitation energy, GeV */
     uint8_t absent[NDET];       /* nonzero: no chamber in this slot */
     uint8_t pad2_[4];
+    double m_ke;                /* decision margin: kinetic energy left after a layer's
+                                   loss within this fraction of the energy before it */
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -291,8 +293,10 @@ static double bethe(double p, double m, const ocfg *g)
  * momentum before the step.  q/pT scales by p/p'.  Its covariance row and
  * column scale by d(q/pT')/d(q/pT) with the loss held fixed, (p/p')^3 E'/E,
  * and the diagonal element by the square.  Returns 0 (state untouched) if
- * the energy would not exceed the mass. */
-static int eloss(double p[5], double C[5][5], const ocfg *g, int dir)
+ * the energy would not exceed the mass.  Outward, a kinetic energy left
+ * within the margin m_ke of what it was raises FL_P4 in *lf: there the stop
+ * decision and the new momentum hinge on the last digits of the loss. */
+static int eloss(double p[5], double C[5][5], const ocfg *g, int dir, unsigned *lf)
 {
     double s = p[2], t = p[3], c = p[4];
     if (c == 0.0 || !(g->eloss_xrho > 0.0)) return 1;
@@ -301,6 +305,7 @@ static int eloss(double p[5], double C[5][5], const ocfg *g, int dir)
     double E = sqrt(pp * pp + m * m);
     double dE = bethe(pp, m, g) * g->eloss_xrho * sqrt(tt) / f;
     double E2 = dir > 0 ? E - dE : E + dE;
+    if (lf && dir > 0 && fabs(E2 - m) <= g->m_ke * (E - m)) *lf |= FL_P4;
     if (!(E2 > m)) return 0;
     double p2 = sqrt(E2 * E2 - m * m);
     double k = pp / p2;
@@ -643,7 +648,7 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
         }
         if (!stop) {
             add_ms(p, C, g);
-            if (!eloss(p, C, g, 1)) {
+            if (!eloss(p, C, g, 1, &lf)) {
                 status |= ST_STOPPED;
                 stop = 1;
             }
@@ -852,7 +857,7 @@ static int hyp_predict(const ocfg *g, hyp_t *h, int l, unsigned *lf)
         if (!propagate(h->p, h->C, &h->x, xl, g, lf, NULL)) { h->status |= ST_STOP_SNP; return 0; }
     }
     add_ms(h->p, h->C, g);
-    if (!eloss(h->p, h->C, g, 1)) {
+    if (!eloss(h->p, h->C, g, 1, lf)) {
         h->status |= ST_STOPPED;
         return 0;
     }
@@ -1171,7 +1176,7 @@ static void refit_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
             }
             if (l > 0) {
                 add_ms(p, C, g);
-                eloss(p, C, g, -1);
+                eloss(p, C, g, -1, NULL);
             }
         }
     }
@@ -1349,7 +1354,7 @@ int oracle_eloss(const ocfg *g, double *p, double *cpk, int dir)
 {
     double C[5][5];
     unpack(cpk, C);
-    int ok = eloss(p, C, g, dir);
+    int ok = eloss(p, C, g, dir, NULL);
     pack(C, cpk);
     return ok;
 }

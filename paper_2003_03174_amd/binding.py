@@ -19,7 +19,7 @@ TRD_OK, TRD_EINVAL, TRD_ENOMEM, TRD_EDEVICE, TRD_ESTATE, TRD_EBUDGET = 0, -1, -2
 TRD_PREC_FP64, TRD_PREC_FP32, TRD_PREC_FP32_COV64 = 0, 1, 2
 PRECISIONS = {"fp64": TRD_PREC_FP64, "fp32": TRD_PREC_FP32, "fp32_cov64": TRD_PREC_FP32_COV64}
 TRK_STOP_SNP, TRK_ROT_FAIL, TRK_OUT_OF_Z, TRK_FP64_FALLBACK, TRK_NOT_PD, TRK_BAD_INPUT = 1, 2, 4, 8, 16, 32
-TRK_REFIT_FEW, TRK_REFIT_SKIP = 64, 128
+TRK_REFIT_FEW, TRK_REFIT_SKIP, TRK_STOPPED = 64, 128, 256
 # TRD-only refit defaults: starting covariance diag (cm^2, cm^2, -, -, (c/GeV)^2), fewest tracklets
 REFIT_COV = (1.0, 100.0, 1e-2, 1e-2, 1.0)
 REFIT_MIN = 4
@@ -62,6 +62,8 @@ class trd_config(C.Structure):
         ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32),
         ("tpc_x_in", C.c_double), ("tpc_x_out", C.c_double), ("tpc_n_rows", C.c_int32),
         ("vox_nx", C.c_int32), ("vox_ny", C.c_int32), ("vox_nz", C.c_int32), ("vox_min", C.c_int32),
+        ("eloss_xrho", C.c_double), ("eloss_za", C.c_double), ("eloss_i", C.c_double),
+        ("chamber_absent", C.c_uint8 * 540),
     ]
 
 
@@ -179,6 +181,13 @@ def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, searc
     c.tpc_x_in, c.tpc_x_out, c.tpc_n_rows = float(tpc["x_in"]), float(tpc["x_out"]), int(tpc["n_rows"])
     c.vox_nx, c.vox_ny, c.vox_nz = (int(v) for v in params.get("voxels", VOXELS))
     c.vox_min = int(params.get("vox_min", VOXEL_MIN))
+    c.eloss_xrho = float(params.get("eloss_xrho", 0.0))
+    c.eloss_za = float(params.get("eloss_za", 0.5))
+    c.eloss_i = float(params.get("eloss_i", 1e-7))
+    ab = params.get("absent")
+    if ab is not None:
+        for d, v in enumerate(list(ab)[:540]):
+            c.chamber_absent[d] = 1 if v else 0
     return c
 
 

@@ -102,6 +102,10 @@ int check_config(const trd_config *c)
         c->tpc_n_rows > 65535 || c->vox_nx < 1 || c->vox_ny < 1 || c->vox_nz < 1 || c->vox_min < 1)
         return TRD_EINVAL;
     if ((int64_t)TRD_N_SECTORS * c->vox_nx * c->vox_ny * c->vox_nz > kMaxVoxels) return TRD_EINVAL;
+    if (!(c->eloss_xrho >= 0 && c->eloss_xrho < 1e6)) return TRD_EINVAL;
+    if (c->eloss_xrho > 0 && !(c->eloss_za > 0 && c->eloss_za < 2 && c->eloss_i > 0 && c->eloss_i < 1 &&
+                               c->mass > 0 && isfinite(c->eloss_i)))
+        return TRD_EINVAL;
     return TRD_OK;
 }
 
@@ -121,6 +125,11 @@ void fill_devcfg(DevCfg<T> &g, const trd_config &c, const T *dx)
     g.k_curv = (T)(-2.99792458e-3 * c.bz);
     g.x_over_x0 = (T)c.x_over_x0;
     g.mass2 = (T)(c.mass * c.mass);
+    g.eloss_xrho = (T)c.eloss_xrho;
+    g.eloss_kza = (T)(0.307075e-3 * c.eloss_za);
+    g.inv_i2 = c.eloss_xrho > 0 ? (T)(1.0 / (c.eloss_i * c.eloss_i)) : (T)0;
+    g.mass = (T)c.mass;
+    g.me_over_m = c.mass > 0 ? (T)(0.51099895e-3 / c.mass) : (T)0;
     for (int k = 0; k < 3; k++) {
         g.sigma_y[k] = (T)c.sigma_y[k];
         g.sigma_dy[k] = (T)c.sigma_dy[k];
@@ -148,6 +157,9 @@ void fill_devcfg(DevCfg<T> &g, const trd_config &c, const T *dx)
     g.bin.n_db = c.n_db;
     g.bin.n_groups = 1;
     g.bin.n_cells = 0;
+    for (int w = 0; w < kAbsentWords; w++) g.bin.absent[w] = 0;
+    for (int d = 0; d < TRD_N_DET; d++)
+        if (c.chamber_absent[d]) g.bin.absent[d >> 5] |= 1u << (d & 31);
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? TRD_OK : TRD_EDEVICE; }

@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t cell_key(float y, float z, float dy, uint32_
 {
     const uint32_t det = det_row >> 5, row = det_row & 31u;
     if (det >= (uint32_t)kDet || row >= (uint32_t)b.n_rows || grp < 0 || grp >= b.n_groups ||
-        !__builtin_isfinite(y) || !__builtin_isfinite(z) || !__builtin_isfinite(dy))
+        !__builtin_isfinite(y) || !__builtin_isfinite(z) || !__builtin_isfinite(dy) || slot_absent(b, (int)det))
         return b.n_cells;
     // bins in double: the float value widened, a power-of-two scale, floor
     const double u = floor(((double)y - b.y_min) * b.inv_w);

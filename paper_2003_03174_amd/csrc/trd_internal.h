@@ -13,7 +13,8 @@ constexpr int kDet = 540;
 
 // per-track status bits (same values as TRD_TRK_* of the public header)
 constexpr uint32_t kStopSnp = 1u, kRotFail = 2u, kOutOfZ = 4u, kFallback = 8u, kNotPD = 16u,
-                   kBadInput = 32u, kRefitFew = 64u, kRefitSkip = 128u;
+                   kBadInput = 32u, kRefitFew = 64u, kRefitSkip = 128u, kStopped = 256u;
+constexpr int kAbsentWords = (kDet + 31) / 32;
 
 // Cell geometry of the tracklet binning; the key arithmetic runs in double
 // so that floor() sees the exact difference y - y_min (w is a power of two).
@@ -24,7 +25,13 @@ struct BinCfg {
     double inv_wd;
     int32_t n_rows, n_yb, n_db, n_groups;
     uint32_t n_cells;
+    uint32_t absent[kAbsentWords];  // bit d: chamber slot d has no chamber
 };
+
+__host__ __device__ inline bool slot_absent(const BinCfg &b, int det)
+{
+    return (b.absent[det >> 5] >> (det & 31)) & 1u;
+}
 
 // Matching parameters, converted once to the state precision T.
 template <typename T>
@@ -34,6 +41,8 @@ struct DevCfg {
     T z_min, z_max, pad_len, inv_pad, vz;  // vz = pad_len^2 / 12
     T drift_len, k_curv;                   // k_curv = -kappa * Bz
     T x_over_x0, mass2;
+    // energy loss: eloss_xrho (g/cm^2, 0 = off), K Z/A, 1/I^2, m, m_e/m
+    T eloss_xrho, eloss_kza, inv_i2, mass, me_over_m;
     T sigma_y[3], sigma_dy[3], tan_psi;
     T chi2_max, n_sigma_dy, n_sigma_road, snp_max;
     T chi2_penalty;                            // cost of a layer without a tracklet (hypotheses)

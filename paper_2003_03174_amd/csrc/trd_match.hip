@@ -49,8 +49,35 @@ __device__ __forceinline__ int int_of(double v) { return (int)v; }
 __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double div_(double a, double b) { return a / b; }
 
+// sin(u)/u, asin(h)/h and (sin d - d)/d^2 of the helix step.  The float
+// forms use their Taylor series where the turning angle is small (|u| < 0.5:
+// first omitted term below 3e-11; h < 0.3: below 1e-8) and the library
+// functions beyond, which costs a fraction of the library's argument
+// reduction; the double forms call the library (gfun: series below 0.5).
 template <typename T> __device__ __forceinline__ T sinc_(T u) { return u == T(0) ? T(1) : div_(T(sin(u)), u); }
+__device__ __forceinline__ float sinc_(float u)
+{
+    const float u2 = u * u;
+    if (u2 < 0.25f)
+        return 1.f + u2 * (-1.f / 6.f + u2 * (1.f / 120.f + u2 * (-1.f / 5040.f + u2 * (1.f / 362880.f))));
+    return div_(sinf(u), u);
+}
+__device__ __forceinline__ float asin_over(float h)
+{
+    const float h2 = h * h;
+    if (h2 < 0.09f)
+        return 1.f + h2 * (1.f / 6.f + h2 * (3.f / 40.f + h2 * (5.f / 112.f + h2 * (35.f / 1152.f + h2 * (63.f / 2816.f)))));
+    return div_(asinf(h), h);
+}
+__device__ __forceinline__ double asin_over(double h) { return h > 0.0 ? asin(h) / h : 1.0; }
 
+__device__ __forceinline__ float gfun(float d)
+{
+    const float d2 = d * d;
+    if (d2 < 0.25f)
+        return d * (-1.f / 6.f + d2 * (1.f / 120.f + d2 * (-1.f / 5040.f + d2 * (1.f / 362880.f + d2 * (-1.f / 39916800.f)))));
+    return div_(sinf(d) - d, d2);
+}
 // (sin d - d) / d^2; Taylor series below |d| = 0.5 where the direct form cancels
 template <typename T> __device__ __forceinline__ T gfun(T d)
 {
@@ -85,7 +112,7 @@ __device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS
     const TS dy = div_(dx * (s1 + s2), ff);
     const TS chord = sqrt(dx * dx + dy * dy);
     const TS h = TS(0.5) * fabs(cu) * chord;
-    const TS aoh = h > TS(0) ? div_(TS(asin(h)), h) : TS(1);
+    const TS aoh = asin_over(h);
     const TS arc = (dx >= TS(0) ? chord : -chord) * aoh;
     const TS delta = cu * arc;
     const TS t = T.t;
@@ -191,6 +218,51 @@ __device__ __forceinline__ void add_ms(Trk<TS, TC> &T, const DevCfg<TS> &g)
     T.C[TT] += th2 * tt * tt;
     T.C[CC] += th2 * c * c * t * t;
     T.C[TC_] += th2 * tt * c * t;
+}
+
+// Mean energy loss of the layer's material at the current point (Bethe
+// formula without density or shell terms; rate at the momentum before the
+// loss; path = thickness / (cos lambda cos phi)).  Outward the energy falls
+// by it, inward (the refit) it is given back.  q/pT scales by p/p', its
+// covariance row by (p/p')^3 E'/E (the loss held fixed).  False (state
+// untouched): the energy would not exceed the mass.
+template <typename TS, typename TC>
+__device__ __forceinline__ bool eloss(Trk<TS, TC> &T, const DevCfg<TS> &g, bool outward)
+{
+    const TS c = T.c;
+    if (!(g.eloss_xrho > TS(0)) || c == TS(0)) return true;
+    const TS s = T.s, t = T.t;
+    const TS f = sqrt(TS(1) - s * s), tt = TS(1) + t * t;
+    const TS p2 = div_(tt, c * c);
+    const TS e2 = p2 + g.mass2;
+    const TS e = sqrt(e2), p = sqrt(p2);
+    const TS bg2 = div_(p2, g.mass2), b2 = div_(p2, e2), gam = div_(e, g.mass), r = g.me_over_m;
+    const TS wmax = TS(2 * 0.51099895e-3) * bg2 / (TS(1) + TS(2) * gam * r + r * r);
+    TS rate = div_(g.eloss_kza, b2) * (TS(0.5) * log(TS(2 * 0.51099895e-3) * bg2 * wmax * g.inv_i2) - b2);
+    rate = rate > TS(0) ? rate : TS(0);
+    const TS de = rate * g.eloss_xrho * div_(sqrt(tt), f);
+    const TS e1 = outward ? e - de : e + de;
+    if (!(e1 > g.mass)) return false;
+    const TS p1 = sqrt(e1 * e1 - g.mass2);
+    const TS k = div_(p, p1);
+    const TC j = TC(k) * TC(k) * TC(k) * TC(div_(e1, e));
+    T.c = c * k;
+    T.C[YC] *= j;
+    T.C[ZC] *= j;
+    T.C[SC] *= j;
+    T.C[TC_] *= j;
+    T.C[CC] *= j * j;
+    return true;
+}
+
+// Whether the point (sector, z) of layer l lies in a chamber slot without a
+// chamber (outside the stacks in z: no).
+template <typename TS>
+__device__ __forceinline__ bool absent_at(const DevCfg<TS> &g, int sec, int l, TS z)
+{
+    const TS row = floor(div_(z - g.z_min, g.pad_len));
+    if (!(row >= TS(0)) || row >= TS(kStacks * g.bin.n_rows)) return false;
+    return slot_absent(g.bin, sec * (kStacks * kLayers) + ((int)row / g.bin.n_rows) * kLayers + l);
 }
 
 template <typename T> __device__ __forceinline__ T cget(const T *C, int i, int j)
@@ -431,6 +503,10 @@ __device__ __forceinline__ bool predict(Trk<TS, TC> &T, int l, const DevCfg<TS> 
 {
     if (!reach_plane(T, l, g, status)) return false;
     add_ms(T, g);
+    if (!eloss(T, g, true)) {
+        status |= kStopped;
+        return false;
+    }
     return true;
 }
 
@@ -1197,16 +1273,19 @@ __device__ __forceinline__ bool beam_track(const DevCfg<TS> &g, const MatchIO &i
     for (int l = 0; l < kLayers; l++) {
         TopN<TS, N> L;
         L.init(H.cost);
+        bool no_chamber = false;
         if (H.valid && H.live) {
             if (!predict(H.T, l, g, H.status)) {
                 H.live = 0;
             } else {
+                no_chamber = absent_at(g, H.T.sec, l, H.T.z);
                 Road<TS> R;
                 if (open_road(H.T, l, grp, g, H.status, R)) scan_road_flat(R, g, io, L);
             }
         }
-        // survivors: N rounds of a group-wide minimum
-        const TS skip_cost = H.cost + g.chi2_penalty;
+        // survivors: N rounds of a group-wide minimum; a layer whose
+        // predicted point lies in an empty chamber slot costs no penalty
+        const TS skip_cost = H.cost + (no_chamber ? TS(0) : g.chi2_penalty);
         bool skip = H.valid != 0;
         int s_ok = 0, s_par = h, s_j = -1, s_st = 0;
         TS s_cost = TS(0), s_c2 = TS(0);
@@ -1445,7 +1524,10 @@ __global__ void __launch_bounds__(256) k_refit(DevCfg<TS> g, RefitIO io)
                     }
                 }
             }
-            if (l > 0) add_ms(T, g);
+            if (l > 0) {
+                add_ms(T, g);
+                eloss(T, g, false);
+            }
         }
     }
     TS *op = reinterpret_cast<TS *>(io.op);

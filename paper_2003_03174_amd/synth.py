@@ -92,11 +92,15 @@ def absent_522():
     return a
 
 
-def realistic_params(**over):
+def realistic_overrides():
     """Detector model with energy loss and the 522-chamber layout.  The layer
     material is a plastic-like radiator and chamber: 1.2 g/cm^2 (about
     X/X0 = 0.03 at X0 = 40 g/cm^2), Z/A = 0.53, I = 70 eV."""
-    p = dict(eloss_xrho=1.2, eloss_za=0.53, eloss_i=70e-9, absent=absent_522())
+    return dict(eloss_xrho=1.2, eloss_za=0.53, eloss_i=70e-9, absent=absent_522())
+
+
+def realistic_params(**over):
+    p = realistic_overrides()
     p.update(over)
     return default_params(**p)
 
@@ -512,11 +516,11 @@ WORKLOADS = {
                           seed=0, params=dict(y_bin_w=8.0, n_yb=16)),
     "c2_frame_20k": dict(n_tracks=20000, pt_dist="exp", fake_ratio=0.5, ineff_frac=0.1,
                          seed=1, params=dict(y_bin_w=8.0, n_yb=16)),
-    # 8 cm y bins x 1/8 cm deflection bins over +-4 cm: the road of a seed
+    # 8 cm y bins x 1/4 cm deflection bins over +-4 cm: the road of a seed
     # with a 5 cm position error is cut down by the 4 sigma dy window
     "c5_distortion_450k": dict(n_tracks=450000, pt_dist="pow3", fake_ratio=0.5, ineff_frac=0.1,
                                distortion=(5.0, 15.0), seed=4,
-                               params=dict(y_bin_w=8.0, n_yb=16, dy_bin_w=0.125, n_db=64,
+                               params=dict(y_bin_w=8.0, n_yb=16, dy_bin_w=0.25, n_db=32,
                                            n_sigma_road=3.0)),
 }
 
@@ -691,7 +695,7 @@ DESCRIPTIONS = {
     "c2_frame_20k": "pT = 0.3 + Exp(1) GeV/c, 50% uniform fakes, 10% of tracks miss 1-2 layers, "
                     "8 cm y bins",
     "c5_distortion_450k": "pT^-3 above 0.3 GeV/c, 50% uniform fakes, 10% inefficiency, 5-15 cm "
-                          "random (y, z) seed displacement, road 3 sigma, 8 cm y x 1/8 cm dy bins",
+                          "random (y, z) seed displacement, road 3 sigma, 8 cm y x 1/4 cm dy bins",
     "multiframe_64": "64 frames, U[2000, 40000] tracks each, fakes per true tracklet U[0.2, 0.8], "
                      "10% inefficiency, group = frame, 8 cm y bins",
 }

@@ -30,10 +30,13 @@ COV_TOL = {"fp64": 1e-12, "fp32": 5e-2, "fp32_cov64": 5e-2}
 
 # decision margins the oracle uses to flag tracks for each precision (the
 # absolute terms follow from the state tolerance: 1e-5 * 10 cm on y and z)
+# (m_ke: a track left with less than this fraction of its kinetic energy by a
+# layer's loss has a momentum whose relative error is the precision's times
+# the inverse fraction: 1e-3 keeps double within 1e-12, 0.02 float within 1e-5)
 MARGINS = {
-    "fp64": dict(margin_rel=1e-4),
-    "fp32": dict(margin_rel=1e-4, m_len=1e-3, m_dy=2e-4, m_chi2=2e-2, m_snp=1e-5),
-    "fp32_cov64": dict(margin_rel=1e-4, m_len=1e-3, m_dy=2e-4, m_chi2=2e-2, m_snp=1e-5),
+    "fp64": dict(margin_rel=1e-4, m_ke=1e-3),
+    "fp32": dict(margin_rel=1e-4, m_len=1e-3, m_dy=2e-4, m_chi2=2e-2, m_snp=1e-5, m_ke=2e-2),
+    "fp32_cov64": dict(margin_rel=1e-4, m_len=1e-3, m_dy=2e-4, m_chi2=2e-2, m_snp=1e-5, m_ke=2e-2),
 }
 
 

@@ -29,8 +29,9 @@ def test_library_exports_every_declared_function():
 def test_config_struct_size_matches_header_layout():
     # 2 ints + 12 doubles + 2 doubles + 4 ints + 3 doubles + 540 + 3 + 3+3+1 + 4 doubles + u64 + 2 ints
     # + n_hyp (int, padded) + chi2_penalty + refit_cov[5] + refit_min (int, padded)
-    # + tpc_x_in, tpc_x_out + 5 ints (padded)
-    assert C.sizeof(B.trd_config) == 8 + 8 * 12 + 16 + 16 + 24 + 8 * 540 + 24 + 56 + 32 + 8 + 8 + 16 + 48 + 40
+    # + tpc_x_in, tpc_x_out + 5 ints (padded) + 3 doubles (energy loss) + 540 bytes (padded to 544)
+    assert C.sizeof(B.trd_config) == (8 + 8 * 12 + 16 + 16 + 24 + 8 * 540 + 24 + 56 + 32 + 8 + 8 + 16 + 48 + 40
+                                      + 24 + 544)
 
 
 def test_status_strings():
@@ -69,6 +70,10 @@ def _cfg(**kw):
     lambda c: setattr(c, "vox_nx", 16),          # 18 * 16 * 4 * 3 > 2048 voxels
     lambda c: setattr(c, "vox_min", 0),
     lambda c: c.x_layer.__setitem__(2, float("nan")),
+    lambda c: setattr(c, "eloss_xrho", -1.0),
+    lambda c: (setattr(c, "eloss_xrho", 1.0), setattr(c, "eloss_za", 0.0)),
+    lambda c: (setattr(c, "eloss_xrho", 1.0), setattr(c, "eloss_i", float("nan"))),
+    lambda c: (setattr(c, "eloss_xrho", 1.0), setattr(c, "mass", 0.0)),
 ])
 def test_create_rejects_bad_config(mutate):
     c = _cfg()

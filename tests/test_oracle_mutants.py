@@ -29,12 +29,12 @@ MUTANTS = {
     "tie_to_higher_index": ("(c2 == bchi && j < best_orig)", "(c2 == bchi && j > best_orig)"),
     "bin_rounding": ("double u = floor((v - lo) * (1.0 / w));", "double u = floor((v - lo) * (1.0 / w) + 0.5);"),
     "joseph_drops_kvk": ("for (int a = 0; a < 2; a++)\n                for (int b = 0; b < 2; b++) v += K[i][a] * V[a][b] * K[j][b];", ""),
-    "no_scattering": ("            add_ms(p, C, g);\n            if (!eloss(p, C, g, 1))", "            if (!eloss(p, C, g, 1))"),
+    "no_scattering": ("            add_ms(p, C, g);\n            if (!eloss(p, C, g, 1,", "            if (!eloss(p, C, g, 1,"),
     "beam_first_parent_state": ("*d = H[c->parent];", "*d = H[0];"),
     "beam_cost_not_carried": ("d->cost = c->cost;", ""),
     "beam_sum_holds_cost": ("d->chi2sum += c->chi2;", "d->chi2sum += c->cost;"),
-    "refit_no_scattering": ("                add_ms(p, C, g);\n                eloss(p, C, g, -1);",
-                            "                eloss(p, C, g, -1);"),
+    "refit_no_scattering": ("                add_ms(p, C, g);\n                eloss(p, C, g, -1, NULL);",
+                            "                eloss(p, C, g, -1, NULL);"),
     "refit_chi2_cross_sign": ("(Szz * ry * ry - 2.0 * Syz * ry * rz + Syy * rz * rz) / det2",
                               "(Szz * ry * ry + 2.0 * Syz * ry * rz + Syy * rz * rz) / det2"),
     "refit_tilt_sign": ("const double ry = ky[j] - (p[0] + tau * (p[1] - kz[j]));",
@@ -48,7 +48,7 @@ MUTANTS = {
     "eloss_no_path_factor": ("* g->eloss_xrho * sqrt(tt) / f;", "* g->eloss_xrho;"),
     "eloss_jacobian_square": ("double j = k * k * k * E2 / E;", "double j = k * k * E2 / E;"),
     "bethe_drops_beta2": ("/ (g->eloss_i * g->eloss_i)) - b2);", "/ (g->eloss_i * g->eloss_i)));"),
-    "refit_no_eloss": ("                eloss(p, C, g, -1);\n", ""),
+    "refit_no_eloss": ("                eloss(p, C, g, -1, NULL);\n", ""),
     "absent_penalty_ignored": ("if (a0) pen = 0.0;", ""),
     "absent_not_dropped": ("!isfinite(dy) || g->absent[det])", "!isfinite(dy))"),
 }

@@ -301,3 +301,17 @@ def test_refit_gives_back_the_energy_inward():
     Q["eloss_xrho"] = 0.0
     r2 = O.refit(Q, o, o["idx"], w, threads=2)
     assert np.median(r2["chi2"][ok]) > 1e-4
+
+
+def test_near_stop_is_flagged():
+    """Tracks left with little kinetic energy by a thick layer carry the
+    margin flag (their momentum hinges on the last digits of the loss)."""
+    w = synth.generate(n_tracks=1500, seed=62, params=dict(eloss_xrho=40.0, eloss_za=0.53, eloss_i=70e-9),
+                       fake_ratio=0.0)
+    a = O.match(w["params"], w, threads=2, margins=dict(margin_rel=0.0, m_ke=0.0))
+    b = O.match(w["params"], w, threads=2, margins=dict(margin_rel=0.0, m_ke=0.05))
+    assert not np.any(a["flags"])
+    fl = (b["flags"] & O.FL_P4) != 0
+    assert 0 < fl.sum() < 0.5 * fl.size
+    # the stopped ones and the survivors hold the same results either way
+    assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(a["p"], b["p"])
