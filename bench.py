@@ -52,18 +52,31 @@ def source_hash():
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per launch of k_match from the committed counter summary, if
+def _profiled(key):
+    """A per-launch figure of k_match from the committed counter summary, if
     it was taken on the current sources (else None)."""
     try:
         text = open(PROFILE).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m = re.search(key + r":\s*([0-9.eE+]+)", text)
     s = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     if not m or not s or s.group(1) != source_hash():
         return None
     return float(m.group(1))
+
+
+def profiled_traffic():
+    """HBM bytes per launch of k_match (FETCH_SIZE and WRITE_SIZE, scaled)."""
+    return _profiled("traffic_bytes_per_launch")
+
+
+def profiled_valu():
+    """Share of the VALU issue slots k_match used and its active-lane share."""
+    a, b = _profiled("valu_issue_frac"), _profiled("valu_lane_frac")
+    if a is None or b is None:
+        return None
+    return {"issue_frac": a, "lane_frac": b, "source": os.path.relpath(PROFILE, ROOT)}
 
 
 def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None, flags=0):
@@ -433,6 +446,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_match_beam" if args.n_hyp else "k_match", "alg_bytes_per_launch": ab,
                      "kernel_ms": kernel_avg},
+        # what bounds k_match instead: its share of the VALU issue slots and
+        # of active lanes per instruction, from the committed counter summary
+        "valu": profiled_valu() if traffic is not None else None,
     }
     if not args.no_fp64 and args.precision != "fp64":
         log("timing the plain FP64 comparator")
