@@ -155,10 +155,12 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Stable scatter of one tile: elements are taken in input order (sub-tile,
-// wavefront, lane); a lane's rank among equal digits of its wavefront comes
-// from eight ballots, the counts of earlier wavefronts and sub-tiles from LDS.
-// The tile is first regrouped by digit in LDS, so that each digit's run goes
-// out as contiguous stores.
+// wavefront, lane).  Each wavefront ranks its lanes among equal digits with
+// eight ballots and records, per sub-tile, the count of each digit it holds;
+// one pass over those counts per digit turns them into the offsets of each
+// (sub-tile, wavefront) within the digit's run, so the whole tile is ranked
+// with four barriers.  The tile is regrouped by digit in LDS, so that each
+// digit's run goes out as contiguous stores.
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
     k_radix_scatter(Src src, int64_t n, int shift, const uint32_t *__restrict__ hist,
@@ -166,21 +168,19 @@ __global__ void __launch_bounds__(kBlock)
                     typename Src::Rec *__restrict__ recs_out, uint32_t *__restrict__ rank_out)
 {
     using Rec = typename Src::Rec;
-    __shared__ uint32_t run[kBins];      // elements of each digit placed so far in this tile
-    __shared__ uint32_t loc[kBins];      // first LDS slot of each digit in this tile
-    __shared__ uint32_t glob[kBins];     // first global position of each digit for this tile
-    __shared__ uint32_t wcnt[kBlock / 64][kBins];
+    constexpr int kWaves = kBlock / 64;
+    __shared__ uint32_t loc[kBins];                  // first LDS slot of each digit in this tile
+    __shared__ uint32_t glob[kBins];                 // first global position of each digit for this tile
+    __shared__ uint16_t cnt[kSub * kWaves][kBins];   // per (sub-tile, wavefront): count, then offset
     __shared__ uint32_t skey[kSortTile];
     __shared__ Rec srec[kSortTile];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t cnt = hist[(int64_t)tid * gridDim.x + blockIdx.x];
+    const uint32_t hc = hist[(int64_t)tid * gridDim.x + blockIdx.x];
     uint32_t tot;
-    loc[tid] = block_excl_scan(cnt, &tot);
+    loc[tid] = block_excl_scan(hc, &tot);
     glob[tid] = hist_off[(int64_t)tid * gridDim.x + blockIdx.x];
-    run[tid] = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; w++) wcnt[w][tid] = 0;
-    __syncthreads();
+    for (int q = 0; q < kSub * kWaves; q++) cnt[q][tid] = 0;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     // all of this thread's elements in flight at once
@@ -193,38 +193,44 @@ __global__ void __launch_bounds__(kBlock)
         rv[j] = Rec{};
         if (e < n) src.load(e, kv[j], rv[j]);
     }
+    __syncthreads();
+    // rank within the wavefront; the first lane of each digit records its count
+    uint32_t rk[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
-        const int64_t e = base + j * kBlock + tid;
-        const bool valid = e < n;
-        const uint32_t key = kv[j];
-        const Rec rec = rv[j];
-        const uint32_t d = (key >> shift) & (kBins - 1);
+        const bool valid = base + j * kBlock + tid < n;
+        const uint32_t d = (kv[j] >> shift) & (kBins - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < kRadixBits; bit++) {
             const uint64_t m = __ballot((d >> bit) & 1u);
             peers &= ((d >> bit) & 1u) ? m : ~m;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t r = run[d] + rank;
-            for (int w = 0; w < wv; w++) r += wcnt[w][d];
-            skey[loc[d] + r] = key;
-            srec[loc[d] + r] = rec;
-        }
-        __syncthreads();
-        uint32_t t = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; w++) {
-            t += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        run[tid] += t;
-        __syncthreads();
+        rk[j] = (uint32_t)__popcll(peers & lt);
+        if (valid && rk[j] == 0) cnt[j * kWaves + wv][d] = (uint16_t)__popcll(peers);
     }
+    __syncthreads();
+    // per digit: counts in (sub-tile, wavefront) order -> exclusive offsets
+    {
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < kSub * kWaves; q++) {
+            const uint32_t c = cnt[q][tid];
+            cnt[q][tid] = (uint16_t)run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSub; j++) {
+        if (base + j * kBlock + tid < n) {
+            const uint32_t d = (kv[j] >> shift) & (kBins - 1);
+            const uint32_t slot = loc[d] + cnt[j * kWaves + wv][d] + rk[j];
+            skey[slot] = kv[j];
+            srec[slot] = rv[j];
+        }
+    }
+    __syncthreads();
     // slot p holds the (p - loc[d])-th element of digit d in this tile
     const int nv = (int)tot;
     for (int p = tid; p < nv; p += kBlock) {
