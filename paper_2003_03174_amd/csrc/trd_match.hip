@@ -1562,7 +1562,7 @@ __device__ __forceinline__ bool step_state(TS &x, TS &y, TS &z, TS &s, TS t, TS 
     const TS dy = div_(dx * (s1 + s2), f1 + f2);
     const TS chord = sqrt(dx * dx + dy * dy);
     const TS h = TS(0.5) * fabs(cu) * chord;
-    const TS aoh = h > TS(0) ? div_(TS(asin(h)), h) : TS(1);
+    const TS aoh = asin_over(h);
     const TS arc = (dx >= TS(0) ? chord : -chord) * aoh;
     y += dy;
     z += t * arc;
@@ -1587,12 +1587,17 @@ __device__ __forceinline__ bool turn_state(TS &x, TS &y, TS &s, bool up, const D
     return true;
 }
 
-// One lane per reference track, walking its clusters inward; the 8 sums of
+// One lane per reference track, walking its clusters inward.  The 8 sums of
 // every voxel are kept per workgroup in LDS (float) and added to the global
-// double sums at the end.  Grid-stride over the tracks.
-template <typename TS>
-__global__ void __launch_bounds__(256) k_residual_sums(DevCfg<TS> g, ResidualIO io)
+// double sums at the end; a lane keeps the sums of the voxel it is in in
+// registers and adds them to LDS only when the walk leaves that voxel (a
+// track stays in one voxel for several pad rows), which cuts the LDS atomics
+// several-fold.  The clusters of a track are fetched kPre at a time ahead of
+// the walk (they do not depend on it).  Grid-stride over the tracks.
+template <typename TS, int kThreads>
+__global__ void __launch_bounds__(kThreads) k_residual_sums(DevCfg<TS> g, ResidualIO io)
 {
+    constexpr int kPre = 8;
     extern __shared__ float ls[];
     const int nsum = io.nvox * kVoxelSums;
     for (int k = threadIdx.x; k < nsum; k += blockDim.x) ls[k] = 0.f;
@@ -1601,6 +1606,20 @@ __global__ void __launch_bounds__(256) k_residual_sums(DevCfg<TS> g, ResidualIO 
     const TS *rx = reinterpret_cast<const TS *>(io.rx);
     const TS step = TS(io.x_out - io.x_in) / TS(io.n_rows - 1);
     const TS fxs = TS(io.nx) / TS(io.x_out - io.x_in);
+    int vox = -1;  // voxel whose sums the lane holds
+    float acc[kVoxelSums];
+#pragma unroll
+    for (int q = 0; q < kVoxelSums; q++) acc[q] = 0.f;
+    auto flush = [&]() {
+        if (vox >= 0) {
+            float *S = ls + kVoxelSums * vox;
+#pragma unroll
+            for (int q = 0; q < kVoxelSums; q++) {
+                atomicAdd(&S[q], acc[q]);
+                acc[q] = 0.f;
+            }
+        }
+    };
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < io.n;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (io.rstatus[i] != 0) continue;
@@ -1608,38 +1627,67 @@ __global__ void __launch_bounds__(256) k_residual_sums(DevCfg<TS> g, ResidualIO 
         TS x = rx[i];
         int sec = io.rsec[i];
         if (sec < 0 || sec >= kSectors) continue;
-        for (int64_t k = io.first[i]; k < io.first[i + 1]; k++) {
-            const uint32_t rs = io.row_sec[k];
-            const int csec = (int)(rs >> 16), row = (int)(rs & 0xffffu);
-            if (csec >= kSectors || row >= io.n_rows) continue;
-            const TS xr = TS(io.x_out) - TS(row) * step;
-            if (csec != sec) {
-                const int d = (csec - sec + kSectors) % kSectors;
-                if (d != 1 && d != kSectors - 1) continue;
-                if (!turn_state(x, y, sn, d == 1, g)) break;
-                sec = csec;
+        const int64_t kend = io.first[i + 1];
+        bool live = true;
+        for (int64_t k0 = io.first[i]; live && k0 < kend; k0 += kPre) {
+            uint32_t rsv[kPre];
+            float cyv[kPre], czv[kPre];
+#pragma unroll
+            for (int u = 0; u < kPre; u++) {
+                rsv[u] = 0xffffffffu;
+                cyv[u] = czv[u] = 0.f;
+                if (k0 + u < kend) {
+                    rsv[u] = io.row_sec[k0 + u];
+                    cyv[u] = io.cy[k0 + u];
+                    czv[u] = io.cz[k0 + u];
+                }
             }
-            if (!step_state(x, y, z, sn, t, c, xr, g)) break;
-            const TS f = sqrt(TS(1) - sn * sn);
-            const TS ty = div_(sn, f), tz = div_(t, f);
-            const TS ry = TS(io.cy[k]) - y, rz = TS(io.cz[k]) - z;
-            const TS fx = (xr - TS(io.x_in)) * fxs;
-            const TS fy = (div_(div_(y, xr), g.tan_half_sector) + TS(1)) * TS(0.5) * TS(io.ny);
-            const TS fz = (div_(z, xr) + TS(1)) * TS(0.5) * TS(io.nz);
-            const int ix = fx < TS(0) ? 0 : (fx >= TS(io.nx) ? io.nx - 1 : (int)fx);
-            const int iy = fy < TS(0) ? 0 : (fy >= TS(io.ny) ? io.ny - 1 : (int)fy);
-            const int iz = fz < TS(0) ? 0 : (fz >= TS(io.nz) ? io.nz - 1 : (int)fz);
-            float *S = ls + kVoxelSums * (((sec * io.nx + ix) * io.ny + iy) * io.nz + iz);
-            atomicAdd(&S[0], 1.f);
-            atomicAdd(&S[1], float(ty));
-            atomicAdd(&S[2], float(tz));
-            atomicAdd(&S[3], float(ty * ty + tz * tz));
-            atomicAdd(&S[4], float(ry));
-            atomicAdd(&S[5], float(rz));
-            atomicAdd(&S[6], float(ty * ry + tz * rz));
-            atomicAdd(&S[7], float(ry * ry + rz * rz));
+#pragma unroll
+            for (int u = 0; u < kPre; u++) {
+                if (!live) continue;
+                const uint32_t rs = rsv[u];
+                const int csec = (int)(rs >> 16), row = (int)(rs & 0xffffu);
+                if (csec >= kSectors || row >= io.n_rows) continue;
+                const TS xr = TS(io.x_out) - TS(row) * step;
+                if (csec != sec) {
+                    const int d = (csec - sec + kSectors) % kSectors;
+                    if (d != 1 && d != kSectors - 1) continue;
+                    if (!turn_state(x, y, sn, d == 1, g)) {
+                        live = false;
+                        continue;
+                    }
+                    sec = csec;
+                }
+                if (!step_state(x, y, z, sn, t, c, xr, g)) {
+                    live = false;
+                    continue;
+                }
+                const TS f = sqrt(TS(1) - sn * sn);
+                const TS ty = div_(sn, f), tz = div_(t, f);
+                const TS ry = TS(cyv[u]) - y, rz = TS(czv[u]) - z;
+                const TS fx = (xr - TS(io.x_in)) * fxs;
+                const TS fy = (div_(div_(y, xr), g.tan_half_sector) + TS(1)) * TS(0.5) * TS(io.ny);
+                const TS fz = (div_(z, xr) + TS(1)) * TS(0.5) * TS(io.nz);
+                const int ix = fx < TS(0) ? 0 : (fx >= TS(io.nx) ? io.nx - 1 : (int)fx);
+                const int iy = fy < TS(0) ? 0 : (fy >= TS(io.ny) ? io.ny - 1 : (int)fy);
+                const int iz = fz < TS(0) ? 0 : (fz >= TS(io.nz) ? io.nz - 1 : (int)fz);
+                const int v = ((sec * io.nx + ix) * io.ny + iy) * io.nz + iz;
+                if (v != vox) {
+                    flush();
+                    vox = v;
+                }
+                acc[0] += 1.f;
+                acc[1] += float(ty);
+                acc[2] += float(tz);
+                acc[3] += float(ty * ty + tz * tz);
+                acc[4] += float(ry);
+                acc[5] += float(rz);
+                acc[6] += float(ty * ry + tz * rz);
+                acc[7] += float(ry * ry + rz * rz);
+            }
         }
     }
+    flush();
     __syncthreads();
     for (int k = threadIdx.x; k < nsum; k += blockDim.x) {
         const float v = ls[k];
@@ -1777,14 +1825,17 @@ void launch_residual_sums(int precision, const DevCfg<double> &gd, const DevCfg<
                           const ResidualIO &io, int n_cu, hipStream_t s)
 {
     if (io.n <= 0) return;
+    constexpr int kThreads = 1024;
     const size_t lds = sizeof(float) * (size_t)io.nvox * kVoxelSums;
-    int64_t blocks = (io.n + 255) / 256;
+    int64_t blocks = (io.n + kThreads - 1) / kThreads;
     const int64_t cap = 2 * (int64_t)(n_cu > 0 ? n_cu : 1);
     if (blocks > cap) blocks = cap;
     if (precision == 0)
-        hipLaunchKernelGGL(k_residual_sums<double>, dim3((unsigned)blocks), dim3(256), lds, s, gd, io);
+        hipLaunchKernelGGL((k_residual_sums<double, kThreads>), dim3((unsigned)blocks), dim3(kThreads), lds, s, gd,
+                           io);
     else
-        hipLaunchKernelGGL(k_residual_sums<float>, dim3((unsigned)blocks), dim3(256), lds, s, gf, io);
+        hipLaunchKernelGGL((k_residual_sums<float, kThreads>), dim3((unsigned)blocks), dim3(kThreads), lds, s, gf,
+                           io);
 }
 
 void launch_voxel_solve(const double *sums, int nvox, int min_count, float *dist, hipStream_t s)
