@@ -74,8 +74,8 @@ extern "C" {
                                      double-covariance re-run */
 #define TRD_CFG_INPUT_ORDER 8u    /* match the tracks in the caller's order; by default
                                      the one-lane-per-track and the several-hypotheses
-                                     launches first sort them by
-                                     (group, sector, z, y) of the seed so that neighbouring
+                                     launches first sort them by (group, sector,
+                                     |q/pT| class, z, y) of the seed so that neighbouring
                                      lanes read neighbouring cells (results are the same,
                                      bit for bit, and come back in input order) */
 #define TRD_CFG_TIME_KERNEL 16u   /* record HIP events on the launch stream around the

@@ -110,7 +110,7 @@ struct TrkSrc {
     using Rec = uint32_t;
     __device__ __forceinline__ uint32_t key(int64_t e) const
     {
-        return track_order_key(ip[e], ip[n + e], isec[e], igrp ? igrp[e] : 0, n_groups);
+        return track_order_key(ip[e], ip[n + e], ip[4 * n + e], isec[e], igrp ? igrp[e] : 0, n_groups);
     }
     __device__ __forceinline__ void load(int64_t e, uint32_t &k, uint32_t &rec) const
     {

@@ -145,18 +145,23 @@ void launch_residual_sums(int precision, const DevCfg<double> &gd, const DevCfg<
                           const ResidualIO &io, int n_cu, hipStream_t s);
 void launch_voxel_solve(const double *sums, int nvox, int min_count, float *dist, hipStream_t s);
 
-// Processing-order key of a seed: group and sector, then 16 cm in z and 4 cm
-// in y (clamped); rejected seeds get the largest key.
+// Processing-order key of a seed: group and sector, then a class of |q/pT|
+// (road widths grow with the scattering of slow tracks, so a wavefront of
+// similar tracks diverges less), then 32 cm in z and 8 cm in y (clamped);
+// rejected seeds get the largest key.
 template <typename TS>
-__device__ __forceinline__ uint32_t track_order_key(TS y, TS z, int sec, int grp, int32_t n_groups)
+__device__ __forceinline__ uint32_t track_order_key(TS y, TS z, TS c, int sec, int grp, int32_t n_groups)
 {
     uint32_t k = (uint32_t)(n_groups * kSectors) << kOrderPosBits;
     if (sec >= 0 && sec < kSectors && grp >= 0 && grp < n_groups && __builtin_isfinite(y) &&
         __builtin_isfinite(z)) {
-        const TS zs = (z + TS(512)) * TS(0.0625), ys = (y + TS(64)) * TS(0.25);
-        const int zb = zs < TS(0) ? 0 : (zs >= TS(63) ? 63 : (int)zs);
-        const int yb = ys < TS(0) ? 0 : (ys >= TS(31) ? 31 : (int)ys);
-        k = ((uint32_t)(grp * kSectors + sec) << kOrderPosBits) | ((uint32_t)zb << 5) | (uint32_t)yb;
+        const TS zs = (z + TS(512)) * TS(0.03125), ys = (y + TS(64)) * TS(0.125);
+        const int zb = zs < TS(0) ? 0 : (zs >= TS(31) ? 31 : (int)zs);
+        const int yb = ys < TS(0) ? 0 : (ys >= TS(15) ? 15 : (int)ys);
+        const TS ac = fabs(c);
+        const int pb = ac < TS(0.8) ? 0 : (ac < TS(1.6) ? 1 : (ac < TS(2.5) ? 2 : 3));
+        k = ((uint32_t)(grp * kSectors + sec) << kOrderPosBits) | ((uint32_t)pb << 9) | ((uint32_t)zb << 4) |
+            (uint32_t)yb;
     }
     return k;
 }
