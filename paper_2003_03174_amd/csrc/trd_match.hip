@@ -926,10 +926,12 @@ __device__ __forceinline__ unsigned xcd_block()
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
-// Waves per SIMD the one-lane kernels are compiled for: four for the float
-// path (at most 128 registers; the road scan is latency bound, so the extra
-// waves in flight are worth a few spilled registers), the register need of
-// the double-covariance paths otherwise.
+// Waves per SIMD the one-lane and the several-hypotheses kernels are
+// compiled for: four for the float path (at most 128 registers; the road scan
+// is latency bound, so the extra waves in flight are worth a few spilled
+// registers: the several-hypotheses kernel drops from 2.06 to 1.40 ms on the
+// 450k batch with four hypotheses), the register need of the
+// double-covariance paths otherwise.
 template <typename TC> constexpr int kMinWaves = sizeof(TC) == 4 ? 4 : 1;
 
 // One lane per track (the plain kernel; double precision runs here).
@@ -1364,7 +1366,7 @@ __device__ __forceinline__ bool beam_track(const DevCfg<TS> &g, const MatchIO &i
 }
 
 template <typename TS, typename TC, int N, bool kFloatCov>
-__global__ void __launch_bounds__(256) k_match_beam(DevCfg<TS> g, MatchIO io)
+__global__ void __launch_bounds__(256, kMinWaves<TC>) k_match_beam(DevCfg<TS> g, MatchIO io)
 {
     const int lane = threadIdx.x & 63, h = lane & (N - 1), base = lane & ~(N - 1);
     const int64_t i = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / N;
@@ -1436,8 +1438,10 @@ namespace {
 // the covariance reset, propagation to each layer plane, a turn into the
 // tracklet's sector when it is a neighbour, the precise step and the update,
 // then the layer's scattering (none below layer 0).  Covariance in double.
+// (Float state: compiled for three waves per SIMD, 3 % faster than two; four
+// spill.)
 template <typename TS>
-__global__ void __launch_bounds__(256) k_refit(DevCfg<TS> g, RefitIO io)
+__global__ void __launch_bounds__(256, sizeof(TS) == 4 ? 3 : 1) k_refit(DevCfg<TS> g, RefitIO io)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= io.n) return;
