@@ -926,17 +926,19 @@ __device__ __forceinline__ unsigned xcd_block()
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
-// Waves per SIMD the one-lane and the several-hypotheses kernels are
-// compiled for: four for the float path (at most 128 registers; the road scan
-// is latency bound, so the extra waves in flight are worth a few spilled
-// registers: the several-hypotheses kernel drops from 2.06 to 1.40 ms on the
-// 450k batch with four hypotheses), the register need of the
-// double-covariance paths otherwise.
-template <typename TC> constexpr int kMinWaves = sizeof(TC) == 4 ? 4 : 1;
+// Waves per SIMD the one-lane kernels are compiled for.  Float state and
+// covariance: four (at most 128 registers; the road scan is latency bound, so
+// the extra waves in flight are worth a few spilled registers; the
+// several-hypotheses kernel takes four too: 2.06 -> 1.40 ms on the 450k
+// batch with four hypotheses).  Float state with a double covariance: three
+// (0.56 -> 0.49 ms).  Double state: the compiler's choice (two; three or
+// four spill and lose 10-20 %).
+template <typename TS, typename TC>
+constexpr int kMinWaves = sizeof(TC) == 4 ? 4 : (sizeof(TS) == 4 ? 3 : 1);
 
 // One lane per track (the plain kernel; double precision runs here).
 template <typename TS, typename TC, bool kFloatCov>
-__global__ void __launch_bounds__(256, kMinWaves<TC>) k_match(DevCfg<TS> g, MatchIO io)
+__global__ void __launch_bounds__(256, (kMinWaves<TS, TC>)) k_match(DevCfg<TS> g, MatchIO io)
 {
     const int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     if (i >= io.n) return;
@@ -949,7 +951,7 @@ __global__ void __launch_bounds__(256, kMinWaves<TC>) k_match(DevCfg<TS> g, Matc
 // (each workgroup exits once the counter passes the last block).  The last
 // workgroup to finish clears the counter for the next launch.
 template <typename TS, typename TC, bool kFloatCov>
-__global__ void __launch_bounds__(256, kMinWaves<TC>) k_match_persistent(DevCfg<TS> g, MatchIO io)
+__global__ void __launch_bounds__(256, (kMinWaves<TS, TC>)) k_match_persistent(DevCfg<TS> g, MatchIO io)
 {
     __shared__ uint32_t blk;
     const uint32_t nblk = (uint32_t)((io.n + blockDim.x - 1) / blockDim.x);
@@ -1366,7 +1368,7 @@ __device__ __forceinline__ bool beam_track(const DevCfg<TS> &g, const MatchIO &i
 }
 
 template <typename TS, typename TC, int N, bool kFloatCov>
-__global__ void __launch_bounds__(256, kMinWaves<TC>) k_match_beam(DevCfg<TS> g, MatchIO io)
+__global__ void __launch_bounds__(256, sizeof(TC) == 4 ? 4 : 1) k_match_beam(DevCfg<TS> g, MatchIO io)
 {
     const int lane = threadIdx.x & 63, h = lane & (N - 1), base = lane & ~(N - 1);
     const int64_t i = ((int64_t)xcd_block() * blockDim.x + threadIdx.x) / N;
