@@ -348,8 +348,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the path shards by "
-                                   "frame with no exchange (see DESIGN.md), multi-GPU runs are "
-                                   "not part of it", "n_gpus": args.gpus}))
+                                   "time frame with no exchange between GPUs, and multi-GPU runs "
+                                   "are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
