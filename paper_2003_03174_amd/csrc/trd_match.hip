@@ -234,6 +234,7 @@ __device__ __forceinline__ bool eloss(Trk<TS, TC> &T, const DevCfg<TS> &g, bool 
     const TS s = T.s, t = T.t;
     const TS f = sqrt(TS(1) - s * s), tt = TS(1) + t * t;
     const TS p2 = div_(tt, c * c);
+    if (!(p2 < TS(1e30))) return true;  // |p| beyond 1e15 GeV: no loss worth a digit
     const TS e2 = p2 + g.mass2;
     const TS e = sqrt(e2), p = sqrt(p2);
     const TS bg2 = div_(p2, g.mass2), b2 = div_(p2, e2), gam = div_(e, g.mass), r = g.me_over_m;
