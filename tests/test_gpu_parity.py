@@ -148,6 +148,18 @@ def test_distortion_batch_full_size_sampled():
     assert np.array_equal(w["tkl_layer"][idx[m]], lay[m])
 
 
+def test_fp32_cov64_full_size_sampled():
+    """The float state with a double covariance on the whole 450k batch."""
+    w = workload("c5_distortion_450k")
+    res = run_gpu(w, "fp32_cov64")
+    sel = np.random.default_rng(2).choice(w["n_tracks"], 1500, replace=False)
+    sel.sort()
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32_cov64"], track_slice=sel)
+    rep = pu.compare(ref, res, "fp32_cov64", sel=sel)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+
+
 def test_fp64_full_size_sampled():
     w = workload("c5_distortion_450k")
     res = run_gpu(w, "fp64")

@@ -143,3 +143,17 @@ def test_refit_restores_the_energy_inward(prec):
     else:
         e = dlt / np.sqrt(ref["cov"][list(pu.DIAG)][:, ok])
         assert e.max() <= 1e-3, e.max(axis=1)
+
+
+def test_detector_model_full_size_sampled():
+    """The 450k batch with the detector model, as `bench.py --realistic` times
+    it: 1,500 sampled tracks against the oracle."""
+    w = synth.generate("c5_distortion_450k", params=synth.realistic_overrides())
+    P = w["params"]
+    got = run(w, P, "fp32")
+    assert got["n_valid"] == w["n_tracklets"]
+    sel = np.sort(np.random.default_rng(4).choice(w["n_tracks"], 1500, replace=False))
+    ref = O.match(P, w, threads=0, margins=pu.MARGINS["fp32"], track_slice=sel)
+    rep = pu.compare(ref, got, "fp32", sel=sel)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
