@@ -210,9 +210,10 @@ __device__ __forceinline__ void add_ms(Trk<TS, TC> &T, const DevCfg<TS> &g)
     const TC f = sqrt(TC(1) - s * s);
     const TC tt = TC(1) + t * t;
     const TC pp = div_(TC(sqrt(tt)), TC(fabs(c)));
-    const TC beta = div_(pp, TC(sqrt(pp * pp + TC(g.mass2))));
+    // beta p = p / sqrt(1 + m^2 / p^2), which stays finite where p^2 would overflow
+    const TC pbeta = div_(pp, TC(sqrt(TC(1) + div_(TC(g.mass2), pp * pp))));
     const TC xi = div_(TC(g.x_over_x0) * TC(sqrt(tt)), f);
-    const TC th0 = div_(TC(0.0136), beta * pp) * sqrt(xi) * (TC(1) + TC(0.038) * log(xi));
+    const TC th0 = div_(TC(0.0136), pbeta) * sqrt(xi) * (TC(1) + TC(0.038) * log(xi));
     const TC th2 = th0 * th0;
     T.C[SS] += th2 * f * f * tt;
     T.C[TT] += th2 * tt * tt;

@@ -157,3 +157,21 @@ def test_detector_model_full_size_sampled():
     rep = pu.compare(ref, got, "fp32", sel=sel)
     print(rep.summary())
     assert rep.ok, rep.summary()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_near_infinite_momentum_loses_nothing(prec):
+    """Seeds with |q/pT| = 1e-25 (a float square underflows): straight tracks
+    that lose no measurable energy and are never stopped."""
+    w = dict(workload("frame", 4000, 61))
+    p = w["p"].copy()
+    p[4, :40] = np.where(p[4, :40] < 0, -1e-25, 1e-25)
+    w["p"] = p
+    P = w["params"]
+    got = run(w, P, prec)
+    ref = O.match(P, w, threads=0, margins=pu.MARGINS[prec])
+    assert not np.any(ref["status"][:40] & O.ST_STOPPED)
+    assert not np.any(got["status"][:40] & O.ST_STOPPED)
+    rep = pu.compare(ref, got, prec)
+    print(rep.summary())
+    assert rep.ok, rep.summary()
