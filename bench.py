@@ -284,7 +284,7 @@ def serve_bench(args):
         g = synth.generate_group(np.random.default_rng(ss[i]), P, int(sizes[i]), fake_ratio=0.5,
                                  ineff_frac=0.1)
         w = synth._concat_groups([g], P)
-        pool.append((w["n_tracks"], w["n_tracklets"], serve.frame_arrays(w)))
+        pool.append((w["n_tracks"], w["n_tracklets"], serve.frame_arrays(w, pinned=True)))
     n_fr = int(args.serve_rate * args.serve_seconds)
     t = np.cumsum(rng.exponential(1.0 / args.serve_rate, n_fr))
 

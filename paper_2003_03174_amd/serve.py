@@ -161,9 +161,12 @@ def summarize(done, n_tracks_of):
 # device executor
 # ---------------------------------------------------------------------------
 
-def frame_arrays(w):
-    """Host arrays of one frame (single-group workload dict from synth)."""
-    return dict(
+def frame_arrays(w, pinned=False):
+    """Host arrays of one frame (single-group workload dict from synth).  With
+    pinned=True they are page-locked torch tensors, as a readout that lands
+    frames in DMA-able memory would hand them over: a batch of one such frame
+    is copied to the device without staging."""
+    a = dict(
         p=np.ascontiguousarray(w["p"].astype(np.float32)),
         cov=np.ascontiguousarray(w["cov"].astype(np.float32)),
         x=np.ascontiguousarray(w["x"].astype(np.float32)),
@@ -173,6 +176,10 @@ def frame_arrays(w):
         dy=np.ascontiguousarray(w["tkl_dy"].astype(np.float32)),
         det_row=np.ascontiguousarray(w["tkl_det_row"].astype(np.uint32).view(np.int32)),
     )
+    if pinned:
+        import torch
+        a = {k: torch.from_numpy(v).pin_memory() for k, v in a.items()}
+    return a
 
 
 BYTES_PER_TRACK = 4 * (21 + 2) + 4 * (21 + 6 + 4 + 1 + 6)     # inputs + outputs (float)
@@ -251,8 +258,14 @@ class HipExecutor:
         s, m = S["stream"], S["m"]
         ntr = sum(f.n_tracks for f in frames)
         ntk = sum(f.n_tracklets for f in frames)
-        # stage the batch in the slot's pinned buffers (free: the slot is idle)
+        # a single frame already in page-locked memory goes to the device as
+        # it is (its group ids are all 0); otherwise the batch is staged in the
+        # slot's pinned buffers (free: the slot is idle)
+        direct = (len(frames) == 1 and isinstance(frames[0].data.get("p"), torch.Tensor) and
+                  frames[0].data["p"].dtype == S["din"]["p"].dtype)
         for k, rows in {**self.IN_TRK, **self.IN_TKL}.items():
+            if direct:
+                break
             n = ntr if k in self.IN_TRK else ntk
             hv = self._v(S["hin"][k], rows, n).numpy()
             if k == "group":
@@ -260,7 +273,7 @@ class HipExecutor:
             elif k == "tgroup":
                 parts = [np.full(f.n_tracklets, i, np.int32) for i, f in enumerate(frames)]
             else:
-                parts = [f.data[k] for f in frames]
+                parts = [np.asarray(f.data[k]) for f in frames]
             np.concatenate(parts, axis=-1, out=hv)
         dv = {}
         ev0, ev1, done = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
@@ -269,7 +282,12 @@ class HipExecutor:
             for k, rows in {**self.IN_TRK, **self.IN_TKL}.items():
                 n = ntr if k in self.IN_TRK else ntk
                 dv[k] = self._v(S["din"][k], rows, n)
-                dv[k].copy_(self._v(S["hin"][k], rows, n), non_blocking=True)
+                if not direct:
+                    dv[k].copy_(self._v(S["hin"][k], rows, n), non_blocking=True)
+                elif k in ("group", "tgroup"):
+                    dv[k].zero_()
+                else:
+                    dv[k].copy_(frames[0].data[k].view(dv[k].shape), non_blocking=True)
             ev0.record(s)
             m.load(dv["y"], dv["z"], dv["dy"], dv["det_row"], dv["tgroup"], len(frames), stream=s)
             out = {k: self._v(S["dout"][k], rows, ntr) for k, rows in self.OUT.items()}

@@ -21,7 +21,10 @@ def test_results_identical_alone_and_in_the_mix():
         g = synth.generate_group(np.random.default_rng(ss[i]), P, int(sizes[i]), fake_ratio=0.5,
                                  ineff_frac=0.1)
         w = synth._concat_groups([g], P)
-        frames.append(Frame(i, 0.0005 * i, w["n_tracks"], w["n_tracklets"], frame_arrays(w)))
+        # every other frame in page-locked memory: alone it goes to the device
+        # without staging, in a batch it is staged like the others
+        data = frame_arrays(w, pinned=i % 2 == 0)
+        frames.append(Frame(i, 0.0005 * i, w["n_tracks"], w["n_tracklets"], data))
     ex = HipExecutor(P, "fp32", budget_bytes=4 << 30, n_slots=2)
     done = Scheduler(ex, "continuous").run(frames)
     mixed = dict(ex.results)
