@@ -194,7 +194,7 @@ int64_t tkl_bytes(int64_t n)
 int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1); }
 // tracks are matched in a spatial order (rows of state in, rows of results
 // out) unless the caller keeps its own order or the launch shape has no use
-// for it (several lanes per road, several hypotheses)
+// for it (several lanes per road)
 bool ordered(const trd_config &c)
 {
     return !(c.flags & TRD_CFG_INPUT_ORDER) && c.search_lanes <= 1;

@@ -5,8 +5,8 @@
 // least-significant-digit radix sort over 8-bit digits that carries the
 // 16-byte search record (y, dy, z, input index) along.  Digit histograms
 // live in LDS, ranks come from wavefront ballots, so there are no global
-// atomics.  Cell offsets follow from the run boundaries of the sorted keys
-// and a suffix minimum.  The search road of a track is then a few contiguous
+// atomics.  Cell offsets follow from the run boundaries of the sorted keys,
+// every cell written once.  The search road of a track is then a few contiguous
 // record ranges, one per (stack, dy bin, y bin) holding all its pad rows: the
 // covariance road of Sect. 3 of the paper, enumerated through the cells it
 // overlaps.
@@ -350,8 +350,6 @@ __global__ void __launch_bounds__(kBlock)
     }
     store_items(out, n, base, o);
 }
-
-// ---- suffix minimum (offsets of empty cells = start of the next run) ----
 
 inline unsigned grid_for(int64_t n, int block)
 {
