@@ -161,11 +161,39 @@ def summarize(done, n_tracks_of):
 # device executor
 # ---------------------------------------------------------------------------
 
+IN_TRK = {"p": 5, "cov": 15, "x": 1, "sector": 1, "group": 1}
+IN_TKL = {"y": 1, "z": 1, "dy": 1, "det_row": 1, "tgroup": 1}
+OUT = {"idx": 6, "p": 5, "cov": 15, "x": 1, "sector": 1, "chi2": 1, "chi2_layer": 6, "n_match": 1,
+       "status": 1}
+INT_KEYS = {"sector", "group", "det_row", "tgroup", "idx", "n_match", "status"}
+TKL_FLOAT32 = {"y", "z", "dy"}   # tracklet fields are float whatever the precision
+
+
+def pack_layout(spec, n_of, float_bytes):
+    """Byte layout of a batch's arrays packed into one buffer: key -> (offset,
+    rows, n, kind) with kind "i" (int32), "f32" or "f" (the state's float of
+    float_bytes), each array 256-byte aligned; and the total size.  One copy
+    then moves a whole batch between host and device."""
+    lay, off = {}, 0
+    for k, rows in spec.items():
+        kind = "i" if k in INT_KEYS else ("f32" if k in TKL_FLOAT32 else "f")
+        es = 4 if kind != "f" else float_bytes
+        n = n_of(k)
+        lay[k] = (off, rows, n, kind)
+        off += (rows * n * es + 255) // 256 * 256
+    return lay, off
+
+
+def _in_counts(n_tracks, n_tracklets):
+    return lambda k: n_tracks if k in IN_TRK else n_tracklets
+
+
 def frame_arrays(w, pinned=False):
     """Host arrays of one frame (single-group workload dict from synth).  With
-    pinned=True they are page-locked torch tensors, as a readout that lands
-    frames in DMA-able memory would hand them over: a batch of one such frame
-    is copied to the device without staging."""
+    pinned=True the frame also carries its inputs packed in one page-locked
+    buffer ("_blob", float state), as a readout that lands frames in DMA-able
+    memory would hand them over: a batch of one such frame goes to the device
+    in a single copy, without staging."""
     a = dict(
         p=np.ascontiguousarray(w["p"].astype(np.float32)),
         cov=np.ascontiguousarray(w["cov"].astype(np.float32)),
@@ -178,7 +206,15 @@ def frame_arrays(w, pinned=False):
     )
     if pinned:
         import torch
-        a = {k: torch.from_numpy(v).pin_memory() for k, v in a.items()}
+        n, nt = a["x"].size, a["y"].size
+        lay, size = pack_layout({**IN_TRK, **IN_TKL}, _in_counts(n, nt), 4)
+        blob = torch.zeros(size, dtype=torch.uint8).pin_memory()
+        buf = blob.numpy()
+        for k, (off, rows, cnt, kind) in lay.items():
+            if k in a:
+                dst = buf[off:off + rows * cnt * 4].view(np.int32 if kind == "i" else np.float32)
+                dst[:] = a[k].reshape(-1)
+        a["_blob"] = blob
     return a
 
 
@@ -193,10 +229,7 @@ class HipExecutor:
     at most max_batch_tracks tracks); every batch uses contiguous views of
     exactly its size."""
 
-    IN_TRK = {"p": 5, "cov": 15, "x": 1, "sector": 1, "group": 1}
-    IN_TKL = {"y": 1, "z": 1, "dy": 1, "det_row": 1, "tgroup": 1}
-    OUT = {"idx": 6, "p": 5, "cov": 15, "x": 1, "sector": 1, "chi2": 1, "chi2_layer": 6,
-           "n_match": 1, "status": 1}
+    IN_TRK, IN_TKL, OUT = IN_TRK, IN_TKL, OUT
 
     def __init__(self, params, precision="fp32", budget_bytes=32 << 30, n_slots=2,
                  tracklets_per_track=12.0, max_groups=256, device=0, block_size=0, search_lanes=0,
@@ -217,25 +250,25 @@ class HipExecutor:
         self.cap_tracks = int(min(per_slot // per_track, max_batch_tracks))
         self.cap_tracklets = int(self.cap_tracks * tracklets_per_track)
         dev = torch.device("cuda", device)
-        f = torch.float64 if precision == "fp64" else torch.float32
+        self.float_bytes = 8 if precision == "fp64" else 4
+        self.dtypes = {"i": torch.int32, "f32": torch.float32,
+                       "f": torch.float64 if precision == "fp64" else torch.float32}
         T, K = self.cap_tracks, self.cap_tracklets
-        dt_in = {"p": f, "cov": f, "x": f, "sector": torch.int32, "group": torch.int32,
-                 "y": torch.float32, "z": torch.float32, "dy": torch.float32,
-                 "det_row": torch.int32, "tgroup": torch.int32}
-        dt_out = {"idx": torch.int32, "p": f, "cov": f, "x": f, "sector": torch.int32, "chi2": f,
-                  "chi2_layer": f, "n_match": torch.int32, "status": torch.int32}
+        # each slot: one device and one page-locked buffer for the batch's
+        # inputs, the same for its outputs (a batch moves in one copy each way)
+        _, in_bytes = pack_layout({**self.IN_TRK, **self.IN_TKL}, _in_counts(T, K), self.float_bytes)
+        _, out_bytes = pack_layout(self.OUT, lambda k: T, self.float_bytes)
         self.slots = []
         for _ in range(n_slots):
             m = B.Matcher(params, precision, device=device, block_size=block_size,
                           search_lanes=search_lanes)
             m.reserve(K, max_groups, T)
-            cap = {**{k: c * T for k, c in self.IN_TRK.items()}, **{k: c * K for k, c in self.IN_TKL.items()}}
-            din = {k: torch.empty(cap[k], dtype=dt_in[k], device=dev) for k in cap}
-            hin = {k: torch.empty(cap[k], dtype=dt_in[k], pin_memory=True) for k in cap}
-            dout = {k: torch.empty(c * T, dtype=dt_out[k], device=dev) for k, c in self.OUT.items()}
-            hout = {k: torch.empty(c * T, dtype=dt_out[k], pin_memory=True) for k, c in self.OUT.items()}
-            self.slots.append(dict(m=m, stream=torch.cuda.Stream(device=dev), din=din, hin=hin,
-                                   dout=dout, hout=hout))
+            self.slots.append(dict(
+                m=m, stream=torch.cuda.Stream(device=dev),
+                din=torch.empty(in_bytes, dtype=torch.uint8, device=dev),
+                hin=torch.empty(in_bytes, dtype=torch.uint8, pin_memory=True),
+                dout=torch.empty(out_bytes, dtype=torch.uint8, device=dev),
+                hout=torch.empty(out_bytes, dtype=torch.uint8, pin_memory=True)))
         self.results = {}
 
     # -- capacity ------------------------------------------------------------
@@ -247,9 +280,15 @@ class HipExecutor:
                 sum(f.n_tracks for f in frames) <= self.cap_tracks and
                 sum(f.n_tracklets for f in frames) <= self.cap_tracklets)
 
-    @staticmethod
-    def _v(flat, rows, n):
-        return flat[: rows * n].view(rows, n) if rows > 1 else flat[:n]
+    def _views(self, blob, lay):
+        """Typed [rows][n] (or [n]) views of a packed buffer."""
+        out = {}
+        for k, (off, rows, n, kind) in lay.items():
+            dt = self.dtypes[kind]
+            es = 8 if dt == self.torch.float64 else 4
+            v = blob[off:off + rows * n * es].view(dt)
+            out[k] = v.view(rows, n) if rows > 1 else v
+        return out
 
     # -- execution -----------------------------------------------------------
     def launch(self, slot, frames):
@@ -258,47 +297,37 @@ class HipExecutor:
         s, m = S["stream"], S["m"]
         ntr = sum(f.n_tracks for f in frames)
         ntk = sum(f.n_tracklets for f in frames)
-        # a single frame already in page-locked memory goes to the device as
-        # it is (its group ids are all 0); otherwise the batch is staged in the
-        # slot's pinned buffers (free: the slot is idle)
-        direct = (len(frames) == 1 and isinstance(frames[0].data.get("p"), torch.Tensor) and
-                  frames[0].data["p"].dtype == S["din"]["p"].dtype)
-        for k, rows in {**self.IN_TRK, **self.IN_TKL}.items():
-            if direct:
-                break
-            n = ntr if k in self.IN_TRK else ntk
-            hv = self._v(S["hin"][k], rows, n).numpy()
-            if k == "group":
-                parts = [np.full(f.n_tracks, i, np.int32) for i, f in enumerate(frames)]
-            elif k == "tgroup":
-                parts = [np.full(f.n_tracklets, i, np.int32) for i, f in enumerate(frames)]
-            else:
-                parts = [np.asarray(f.data[k]) for f in frames]
-            np.concatenate(parts, axis=-1, out=hv)
-        dv = {}
+        lay_in, nb_in = pack_layout({**self.IN_TRK, **self.IN_TKL}, _in_counts(ntr, ntk), self.float_bytes)
+        lay_out, nb_out = pack_layout(self.OUT, lambda k: ntr, self.float_bytes)
+        # a single frame that arrived packed in page-locked memory goes to the
+        # device as it is; otherwise the batch is packed into the slot's
+        # pinned buffer (free: the slot is idle)
+        blob = frames[0].data.get("_blob") if len(frames) == 1 else None
+        src = blob if (blob is not None and self.float_bytes == 4) else None
+        if src is None:
+            hv = self._views(S["hin"], lay_in)
+            for k, v in hv.items():
+                if k == "group":
+                    parts = [np.full(f.n_tracks, i, np.int32) for i, f in enumerate(frames)]
+                elif k == "tgroup":
+                    parts = [np.full(f.n_tracklets, i, np.int32) for i, f in enumerate(frames)]
+                else:
+                    parts = [np.asarray(f.data[k]) for f in frames]
+                np.concatenate(parts, axis=-1, out=v.numpy())
+            src = S["hin"]
         ev0, ev1, done = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
                           torch.cuda.Event())
         with torch.cuda.stream(s):
-            for k, rows in {**self.IN_TRK, **self.IN_TKL}.items():
-                n = ntr if k in self.IN_TRK else ntk
-                dv[k] = self._v(S["din"][k], rows, n)
-                if not direct:
-                    dv[k].copy_(self._v(S["hin"][k], rows, n), non_blocking=True)
-                elif k in ("group", "tgroup"):
-                    dv[k].zero_()
-                else:
-                    dv[k].copy_(frames[0].data[k].view(dv[k].shape), non_blocking=True)
+            S["din"][:nb_in].copy_(src[:nb_in], non_blocking=True)
+            dv = self._views(S["din"], lay_in)
             ev0.record(s)
             m.load(dv["y"], dv["z"], dv["dy"], dv["det_row"], dv["tgroup"], len(frames), stream=s)
-            out = {k: self._v(S["dout"][k], rows, ntr) for k, rows in self.OUT.items()}
+            out = self._views(S["dout"], lay_out)
             m.match(dv["p"], dv["cov"], dv["x"], dv["sector"], dv["group"], out=out, stream=s)
             ev1.record(s)
-            host = {}
-            for k, rows in self.OUT.items():
-                host[k] = self._v(S["hout"][k], rows, ntr)
-                host[k].copy_(out[k], non_blocking=True)
+            S["hout"][:nb_out].copy_(S["dout"][:nb_out], non_blocking=True)
             done.record(s)
-        return dict(frames=frames, done=done, ev=(ev0, ev1), host=host)
+        return dict(frames=frames, done=done, ev=(ev0, ev1), host=self._views(S["hout"], lay_out))
 
     def poll(self, h):
         return h["done"].query()
