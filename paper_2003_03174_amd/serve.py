@@ -16,6 +16,7 @@ with launch/poll/collect methods; `HipExecutor` is the device one.
 """
 from __future__ import annotations
 
+import gc
 import math
 import time
 from collections import deque
@@ -59,7 +60,7 @@ class Scheduler:
     """
 
     def __init__(self, executor, policy="continuous", static_frames=8, static_timeout_s=0.02,
-                 clock=time.perf_counter, sleep=time.sleep):
+                 clock=time.perf_counter, sleep=time.sleep, idle_gc=True):
         assert policy in ("continuous", "static")
         self.ex = executor
         self.policy = policy
@@ -67,6 +68,13 @@ class Scheduler:
         self.static_timeout_s = static_timeout_s
         self.clock = clock
         self.sleep = sleep
+        # A full collection of Python's cyclic garbage walks every tracked
+        # object of the process (torch's alone are several hundred thousand)
+        # and stalls the loop for milliseconds.  With idle_gc the automatic
+        # collector is off while `run` serves; the two young generations are
+        # collected only when the loop has nothing to do, and the previous
+        # collector state comes back when `run` returns.
+        self.idle_gc = idle_gc
 
     def _take(self, queue, now):
         """Frames for the next batch (FIFO prefix that fits), or []."""
@@ -87,6 +95,25 @@ class Scheduler:
 
     def run(self, frames, realtime=True):
         """Serve `frames` (sorted by arrival).  Returns a list of Done."""
+        if not self.idle_gc:
+            return self._run(frames, realtime)
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(frames, realtime)
+        finally:
+            if was_enabled:
+                gc.enable()
+
+    def _collect_young(self):
+        young, middle, _ = gc.get_count()
+        th0, th1, _ = gc.get_threshold()
+        if middle >= th1:
+            gc.collect(1)
+        elif young >= th0:
+            gc.collect(0)
+
+    def _run(self, frames, realtime):
         pending = deque(sorted(frames, key=lambda f: f.arrival))
         queue = deque()
         free = list(range(self.ex.n_slots))
@@ -126,6 +153,8 @@ class Scheduler:
                 nbatch += 1
                 progressed = True
             if not progressed:
+                if self.idle_gc:
+                    self._collect_young()
                 if realtime:
                     self.sleep(5e-5)
                 else:
@@ -233,7 +262,11 @@ class HipExecutor:
 
     def __init__(self, params, precision="fp32", budget_bytes=32 << 30, n_slots=2,
                  tracklets_per_track=12.0, max_groups=256, device=0, block_size=0, search_lanes=0,
-                 max_batch_tracks=2_000_000):
+                 max_batch_tracks=2_000_000, on_result=None):
+        """on_result(fid, arrays) receives each frame's results as they are
+        collected; without it they accumulate in `results` until the caller
+        takes them out, which a long-running server must do (every frame
+        holds about 160 bytes per track)."""
         import torch
 
         from . import binding as B
@@ -270,6 +303,7 @@ class HipExecutor:
                 dout=torch.empty(out_bytes, dtype=torch.uint8, device=dev),
                 hout=torch.empty(out_bytes, dtype=torch.uint8, pin_memory=True)))
         self.results = {}
+        self.on_result = on_result
 
     # -- capacity ------------------------------------------------------------
     def frame_fits(self, f):
@@ -340,7 +374,10 @@ class HipExecutor:
             sl = slice(off, off + f.n_tracks)
             r = {k: v.numpy()[..., sl].copy() for k, v in h["host"].items()}
             r["idx"] = np.where(r["idx"] >= 0, r["idx"] - toff, -1).astype(np.int32)
-            self.results[f.fid] = r
+            if self.on_result is not None:
+                self.on_result(f.fid, r)
+            else:
+                self.results[f.fid] = r
             off += f.n_tracks
             toff += f.n_tracklets
         ms = h["ev"][0].elapsed_time(h["ev"][1])

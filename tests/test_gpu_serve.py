@@ -25,9 +25,13 @@ def test_results_identical_alone_and_in_the_mix():
         # without staging, in a batch it is staged like the others
         data = frame_arrays(w, pinned=i % 2 == 0)
         frames.append(Frame(i, 0.0005 * i, w["n_tracks"], w["n_tracklets"], data))
-    ex = HipExecutor(P, "fp32", budget_bytes=4 << 30, n_slots=2)
+    # results of the mix go to a consumer, those of the lone runs stay in
+    # the executor's store
+    mixed = {}
+    ex = HipExecutor(P, "fp32", budget_bytes=4 << 30, n_slots=2, on_result=mixed.__setitem__)
     done = Scheduler(ex, "continuous").run(frames)
-    mixed = dict(ex.results)
+    assert not ex.results and sorted(mixed) == list(range(n))
+    ex.on_result = None
     st = summarize(done, {f.fid: f.n_tracks for f in frames})
     print(st)
     assert st["frames"] == n and st["batches"] < n  # some batches hold several frames

@@ -1,4 +1,7 @@
 """Scheduler of the serving loop on a simulated device (no GPU)."""
+import gc
+import weakref
+
 import numpy as np
 
 from paper_2003_03174_amd.serve import FakeExecutor, Frame, Scheduler, summarize
@@ -57,3 +60,50 @@ def test_static_policy_waits_for_count_or_timeout():
     last = [d for d in done if d.n_frames_in_batch == 2]
     # the timeout runs from the oldest queued frame (arrival 0.008 s)
     assert len(last) == 2 and all(abs(d.launched - (0.008 + 0.05)) < 1e-9 for d in last)
+
+
+class _Cycle:
+    def __init__(self):
+        self.me = self
+
+
+class _GarbageExecutor(FakeExecutor):
+    """Leaves cyclic garbage behind at every launch, as host code does."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.refs = []
+
+    def launch(self, slot, frames):
+        for _ in range(400):
+            c = _Cycle()
+            self.refs.append(weakref.ref(c))
+        return super().launch(slot, frames)
+
+
+def test_idle_collection_frees_young_garbage_and_restores_the_collector():
+    for enabled in (True, False):
+        ex = _GarbageExecutor(cap_tracks=200000, cap_tracklets=2000000, s_per_track=1e-8)
+        (gc.enable if enabled else gc.disable)()
+        try:
+            full_before = gc.get_stats()[2]["collections"]
+            done = Scheduler(ex, "continuous").run(_stream(60, rate=20.0), realtime=False)
+            full_after = gc.get_stats()[2]["collections"]
+            assert gc.isenabled() == enabled
+        finally:
+            gc.enable()
+        assert len(done) == 60
+        # no full collection while serving; the cycles died in idle time
+        assert full_after == full_before
+        dead = sum(r() is None for r in ex.refs)
+        assert dead >= 0.9 * len(ex.refs)
+
+
+def test_idle_collection_off_leaves_the_collector_alone():
+    ex = FakeExecutor(cap_tracks=200000, cap_tracklets=2000000, s_per_track=1e-8)
+    gc.disable()
+    try:
+        Scheduler(ex, "continuous", idle_gc=False).run(_stream(10, rate=20.0), realtime=False)
+        assert not gc.isenabled()
+    finally:
+        gc.enable()
