@@ -20,6 +20,8 @@ _LIB = os.environ.get("TRD_ORACLE_LIB") or os.path.join(_HERE, "libtrd_oracle.so
 ST_STOP_SNP, ST_ROT_FAIL, ST_OUT_OF_Z, ST_BAD_INPUT = 1, 2, 4, 32
 ST_STOPPED = 256
 FL_P1, FL_P2, FL_P3, FL_P4 = 1, 2, 4, 8
+FL_KCUT, FL_KGATE = 16, 32   # the gate a P1/P2 decision concerned: the chi2 cut, a road edge or the dy gate
+FL_DECISIONS = FL_P1 | FL_P2 | FL_P3 | FL_P4
 
 
 class OCfg(C.Structure):

@@ -72,6 +72,9 @@
 #define FL_P2 2u /* a loser fails exactly one gate by a margin and would win */
 #define FL_P3 4u /* near tie between winner and runner-up */
 #define FL_P4 8u /* sector edge, z acceptance or sin(phi) limit near */
+/* which gate a P1 or P2 decision concerned (both can be set) */
+#define FL_KCUT 16u  /* the chi2 cut */
+#define FL_KGATE 32u /* a road edge or the dy gate */
 
 typedef struct {
     double x_layer[NLAY];
@@ -711,6 +714,8 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
             }
             if (best >= 0) {
                 if (bnear) lf |= FL_P1;
+                if (bnear & 8u) lf |= FL_KCUT;
+                if (bnear & 7u) lf |= FL_KGATE;
                 if (second - bchi <= g->m_rel * bchi + g->m_chi2) lf |= FL_P3;
             }
             /* a rejected candidate one marginal gate away from winning */
@@ -720,7 +725,8 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
                 unsigned fail, nm;
                 eval_cand(g, &r, T->y[j], T->z[j], T->dy[j], g->dx_chamber[T->det_row[j] >> 5], &c2, &fail, &nm);
                 if (!fail || popcount4(fail) != 1 || !(fail & nm)) continue;
-                if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2) lf |= FL_P2;
+                if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2)
+                    lf |= FL_P2 | ((fail & 8u) ? FL_KCUT : FL_KGATE);
             }
             if (best >= 0) {
                 int64_t j = best_orig;
@@ -950,8 +956,11 @@ static void match_one_beam(const ocfg *g, int64_t i, int64_t n, const double *ip
                         if (!fail) clist_push(K, Hh->cost + c2, c2, h, j);
                         /* a gate decision within the margins: passing near a
                          * limit, or failing exactly one gate by a margin */
-                        if ((!fail && nm) || (fail && popcount4(fail) == 1 && (fail & nm)))
-                            clist_push(E, Hh->cost + c2, c2, h, fail ? 1 : 0);
+                        if ((!fail && nm) || (fail && popcount4(fail) == 1 && (fail & nm))) {
+                            unsigned near = fail ? (fail & nm) : nm;
+                            clist_push(E, Hh->cost + c2, c2, h,
+                                       (fail ? 1 : 0) | ((near & 8u) ? 2 : 0) | ((near & 7u) ? 4 : 0));
+                        }
                     }
                 }
             }
@@ -977,7 +986,8 @@ static void match_one_beam(const ocfg *g, int64_t i, int64_t n, const double *ip
             flags |= FL_P3;
         for (int64_t a = 0; a < E->n; a++)
             if (E->v[a].cost <= edge + g->m_rel * fabs(edge) + g->m_chi2)
-                flags |= E->v[a].j ? FL_P2 : FL_P1;
+                flags |= ((E->v[a].j & 1) ? FL_P2 : FL_P1) | ((E->v[a].j & 2) ? FL_KCUT : 0u) |
+                         ((E->v[a].j & 4) ? FL_KGATE : 0u);
         for (int k = 0; k < nk; k++) {
             const child_t *c = &K->v[k];
             hyp_t *d = &Hn[k];

@@ -105,6 +105,23 @@ def realistic_params(**over):
     return default_params(**p)
 
 
+def inclined_resolution(psi_deg=8.0):
+    """Tracklet resolutions that depend on the track inclination, with the dy
+    offset of the Lorentz angle (Sect. 3 and Fig. 3: the widths are
+    second-order polynomials in sin(phi), best for tracks at the Lorentz
+    angle, about 8 degrees at 0.5 T).  The figure's coefficients are not in
+    the text; these curves put the minimum at sin(phi) = sin(psi_L):
+    sigma_y = 0.03 cm + 0.5 cm (s - s_L)^2, sigma_dy = 0.0015 cm +
+    0.02 cm (s - s_L)^2 (0.5 mrad over the 3 cm drift at the minimum)."""
+    sl = math.sin(math.radians(psi_deg))
+
+    def around(w0, k):
+        return [w0 + k * sl * sl, -2.0 * k * sl, k]
+
+    return dict(sigma_y=around(0.03, 0.5), sigma_dy=around(0.0015, 0.02),
+                tan_psi=math.tan(math.radians(psi_deg)))
+
+
 def tilt_pm2deg():
     """The paper's +-2 degree pad tilt, alternating sign from layer to layer."""
     t = math.tan(math.radians(2.0))

@@ -51,11 +51,24 @@ MUTANTS = {
     "refit_no_eloss": ("                eloss(p, C, g, -1, NULL);\n", ""),
     "absent_penalty_ignored": ("if (a0) pen = 0.0;", ""),
     "absent_not_dropped": ("!isfinite(dy) || g->absent[det])", "!isfinite(dy))"),
+    "resolution_curvature_linear": ("a[1] * s + a[2] * s * s; }", "a[1] * s + a[2] * s; }"),
+    "resolution_slope_sign": ("return a[0] + a[1] * s + a[2]", "return a[0] - a[1] * s + a[2]"),
+    "lorentz_offset_sign": ("r.dytrk = g->drift_len * (r.tphi - g->tan_psi);",
+                            "r.dytrk = g->drift_len * (r.tphi + g->tan_psi);"),
+    "update_width_at_the_minimum": ("double syu = poly2(g->sigma_y, p[2]);", "double syu = g->sigma_y[0];"),
+    "flag_margin_wider": ("return fabs(a - lim) <= rel * fabs(lim) + abs_;",
+                          "return fabs(a - lim) <= 4.0 * rel * fabs(lim) + abs_;"),
+    "flag_p2_any_loser": ("if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2)\n", "if (1)\n"),
+    "flag_p2_two_gates": ("if (!fail || popcount4(fail) != 1 || !(fail & nm)) continue;",
+                          "if (!fail || !(fail & nm)) continue;"),
+    "flag_p3_dropped": ("if (second - bchi <= g->m_rel * bchi + g->m_chi2) lf |= FL_P3;", ""),
+    "flag_p1_dropped": ("if (bnear) lf |= FL_P1;", ""),
 }
 
 
 PINS = ["test_oracle_math.py", "test_oracle_search.py", "test_oracle_beam.py", "test_oracle_refit.py",
-        "test_oracle_residuals.py", "test_oracle_realistic.py"]
+        "test_oracle_residuals.py", "test_oracle_realistic.py", "test_oracle_resolution.py",
+        "test_oracle_flags.py"]
 
 
 def _run_mutant(name, tmp):
