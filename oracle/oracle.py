@@ -42,6 +42,7 @@ class OCfg(C.Structure):
         ("refit_cov", C.c_double * 5), ("refit_min", C.c_int32), ("pad_", C.c_int32),
         ("eloss_xrho", C.c_double), ("eloss_za", C.c_double), ("eloss_i", C.c_double),
         ("absent", C.c_uint8 * 540), ("pad2_", C.c_uint8 * 4), ("m_ke", C.c_double),
+        ("m_state", C.c_double),
     ]
 
 class OTpc(C.Structure):
@@ -113,7 +114,7 @@ def lib():
     return _lib
 
 
-def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0, m_ke=1e-3):
+def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0, m_ke=1e-3, m_state=0.0):
     c = OCfg()
     P = params
     for l in range(6):
@@ -133,6 +134,7 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
     c.n_sigma_road, c.snp_max = P["n_sigma_road"], P["snp_max"]
     c.m_rel, c.m_len, c.m_dy, c.m_chi2, c.m_snp = margin_rel, m_len, m_dy, m_chi2, m_snp
     c.m_ke = m_ke
+    c.m_state = m_state
     c.n_rows, c.n_yb = P["n_rows"], P["n_yb"]
     c.n_hyp = int(P.get("n_hyp", 0))
     c.chi2_penalty = float(P.get("chi2_penalty", P["chi2_max"]))

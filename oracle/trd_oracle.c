@@ -102,6 +102,9 @@ typedef struct {
     uint8_t pad2_[4];
     double m_ke;                /* decision margin: kinetic energy left after a layer's
                                    loss within this fraction of the energy before it */
+    double m_state;             /* decision margin: relative tolerance of the compared
+                                   path's predicted y and z (floor 10 cm), carried into
+                                   each road's chi2 (0: none) */
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -511,7 +514,33 @@ typedef struct {
     double y, z, s, t, f, tphi, tz, tau;
     double Ry, Rz, gdy, dytrk;
     double Si[2][2];
+    double kchi;   /* chi2 error scale of this road, see road_chi2_scale */
 } road_t;
+
+/* A predicted state whose y, z carry errors up to m_state max(|.|, 10 cm) and
+ * whose sin(phi), tan(lambda) carry errors up to m_state max(|.|, 0.1) moves
+ * the residual r = (r_y, r_z) of a candidate at most dxmax away in x by at
+ * most e = (e_y + |tau| e_z, e_z), with e_y, e_z the errors of the linearly
+ * extrapolated point; a candidate's chi2 = r' S^-1 r then moves by at most
+ * 2 |S^-1/2 r| |S^-1/2 e| + |S^-1/2 e|^2 <= kchi sqrt(chi2) + kchi^2 / 4 with
+ * kchi = 2 |e| / sqrt(lambda_min(S)). */
+static void road_chi2_scale(const ocfg *g, road_t *r, double Syy, double Syz, double Szz, double dxmax)
+{
+    r->kchi = 0.0;
+    if (!(g->m_state > 0.0)) return;
+    const double ds = g->m_state * fmax(fabs(r->s), 0.1), dt = g->m_state * fmax(fabs(r->t), 0.1);
+    const double f3 = r->f * r->f * r->f;
+    const double ez = g->m_state * fmax(fabs(r->z), 10.0) + dxmax * (dt / r->f + fabs(r->t * r->s) * ds / f3);
+    const double ey = g->m_state * fmax(fabs(r->y), 10.0) + dxmax * ds / f3 + fabs(r->tau) * ez;
+    const double h = 0.5 * (Syy - Szz);
+    const double lmin = 0.5 * (Syy + Szz) - sqrt(h * h + Syz * Syz);
+    r->kchi = lmin > 0.0 ? 2.0 * sqrt(ey * ey + ez * ez) / sqrt(lmin) : INFINITY;
+}
+
+static double chi2_err(const road_t *r, double c2)
+{
+    return r->kchi * sqrt(fmax(c2, 0.0)) + 0.25 * r->kchi * r->kchi;
+}
 
 /* Evaluates one candidate.  fail: bit0 y road, bit1 z road, bit2 dy gate,
  * bit3 chi2 cut; nearm: same bits when the value lies within the margin of
@@ -533,7 +562,7 @@ static void eval_cand(const ocfg *g, const road_t *r, double yj, double zj, doub
     if (near_lim(fabs(ry), r->Ry, g->m_rel, g->m_len)) nm |= 1u;
     if (near_lim(fabs(rz), r->Rz, g->m_rel, g->m_len)) nm |= 2u;
     if (near_lim(fabs(ddy), r->gdy, g->m_rel, g->m_dy)) nm |= 4u;
-    if (near_lim(c2, g->chi2_max, g->m_rel, g->m_chi2)) nm |= 8u;
+    if (near_lim(c2, g->chi2_max, g->m_rel, g->m_chi2 + chi2_err(r, g->chi2_max))) nm |= 8u;
     *chi2 = c2;
     *fail = f;
     *nearm = nm;
@@ -681,6 +710,7 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
         r.Ry = g->n_sigma_road * sqrt(Syy);
         r.Rz = g->n_sigma_road * sqrt(Szz);
         r.dytrk = g->drift_len * (r.tphi - g->tan_psi);
+        road_chi2_scale(g, &r, Syy, Syz, Szz, dxmax);
         {
             double sdy = poly2(g->sigma_dy, r.s);
             double f3 = r.f * r.f * r.f;
@@ -716,7 +746,9 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
                 if (bnear) lf |= FL_P1;
                 if (bnear & 8u) lf |= FL_KCUT;
                 if (bnear & 7u) lf |= FL_KGATE;
-                if (second - bchi <= g->m_rel * bchi + g->m_chi2) lf |= FL_P3;
+                if (isfinite(second) &&
+                    second - bchi <= g->m_rel * bchi + g->m_chi2 + chi2_err(&r, bchi) + chi2_err(&r, second))
+                    lf |= FL_P3;
             }
             /* a rejected candidate one marginal gate away from winning */
             for (int64_t a = 0; a < L->n; a++) {
@@ -725,7 +757,7 @@ static void match_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
                 unsigned fail, nm;
                 eval_cand(g, &r, T->y[j], T->z[j], T->dy[j], g->dx_chamber[T->det_row[j] >> 5], &c2, &fail, &nm);
                 if (!fail || popcount4(fail) != 1 || !(fail & nm)) continue;
-                if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2)
+                if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2 + chi2_err(&r, bchi) + chi2_err(&r, c2))
                     lf |= FL_P2 | ((fail & 8u) ? FL_KCUT : FL_KGATE);
             }
             if (best >= 0) {
@@ -871,7 +903,7 @@ static int hyp_predict(const ocfg *g, hyp_t *h, int l, unsigned *lf)
 }
 
 /* Road of a predicted hypothesis (same quantities as the single matcher). */
-static void hyp_road(const ocfg *g, const hyp_t *h, int l, road_t *r)
+static void hyp_road(const ocfg *g, const hyp_t *h, int l, double dxmax, road_t *r)
 {
     r->y = h->p[0]; r->z = h->p[1]; r->s = h->p[2]; r->t = h->p[3];
     r->f = sqrt(1.0 - r->s * r->s);
@@ -890,6 +922,7 @@ static void hyp_road(const ocfg *g, const hyp_t *h, int l, road_t *r)
     r->Ry = g->n_sigma_road * sqrt(Syy);
     r->Rz = g->n_sigma_road * sqrt(Szz);
     r->dytrk = g->drift_len * (r->tphi - g->tan_psi);
+    road_chi2_scale(g, r, Syy, Syz, Szz, dxmax);
     double sdy = poly2(g->sigma_dy, r->s);
     double f3 = r->f * r->f * r->f;
     r->gdy = g->n_sigma_dy * sqrt(sdy * sdy + g->drift_len * g->drift_len * h->C[2][2] / (f3 * f3));
@@ -937,7 +970,7 @@ static void match_one_beam(const ocfg *g, int64_t i, int64_t n, const double *ip
             if (Hh->live) Hh->live = hyp_predict(g, Hh, l, &flags);
             if (Hh->live) {
                 road_t r;
-                hyp_road(g, Hh, l, &r);
+                hyp_road(g, Hh, l, dxmax, &r);
                 double mz = dxmax * fabs(r.tz);
                 double wlo = r.z - r.Rz - mz, whi = r.z + r.Rz + mz, zmax = -g->z_min;
                 if (near_lim(whi, g->z_min, g->m_rel, g->m_len) || near_lim(wlo, zmax, g->m_rel, g->m_len))
@@ -981,6 +1014,8 @@ static void match_one_beam(const ocfg *g, int64_t i, int64_t n, const double *ip
         /* decisions within the margins: the edge of the kept set, the final
          * winner, and gate decisions on children that would be kept */
         double edge = K->v[nk - 1].cost;
+        /* (path costs are sums over the layers: compared with the fixed
+         * absolute margin m_chi2, not the per-road state tolerance) */
         if (K->n > nk && K->v[nk].cost - edge <= g->m_rel * fabs(edge) + g->m_chi2) flags |= FL_P3;
         if (l == NLAY - 1 && nk > 1 && K->v[1].cost - K->v[0].cost <= g->m_rel * fabs(K->v[0].cost) + g->m_chi2)
             flags |= FL_P3;
@@ -1113,6 +1148,15 @@ int oracle_match(const ocfg *g, int64_t n_trk, const double *tp, const double *t
  *     predicted chi2 of the updates;
  *   - fewer than refit_min tracklets: the input state is copied with the
  *     starting covariance and REFIT_FEW. */
+/* The matched tracklet of layer l, or -1: an index is one only if it lies in
+ * [0, n_tkl) and its chamber exists (det < 540) and belongs to layer l. */
+static int32_t refit_index(int32_t j, int l, int64_t n_tkl, const uint32_t *kdr)
+{
+    if (j < 0 || j >= n_tkl) return -1;
+    const uint32_t det = kdr[j] >> 5;
+    return (det < NDET && det % NLAY == (uint32_t)l) ? j : -1;
+}
+
 static void refit_one(const ocfg *g, int64_t i, int64_t n, const double *ip, const double *ix,
                       const int32_t *isec, const int32_t *idx, int64_t n_tkl, const double *ky,
                       const double *kz, const uint32_t *kdr, double *op, double *oc, double *ox,
@@ -1127,10 +1171,8 @@ static void refit_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
         p[k] = ip[k * n + i];
         C[k][k] = g->refit_cov[k];
     }
-    for (int l = 0; l < NLAY; l++) {
-        int32_t j = idx[l * n + i];
-        if (j >= 0 && j < n_tkl) nm++;
-    }
+    for (int l = 0; l < NLAY; l++)
+        if (refit_index(idx[l * n + i], l, n_tkl, kdr) >= 0) nm++;
     int bad = !(isfinite(x) && sec >= 0 && sec < NSEC);
     for (int k = 0; k < 5; k++) bad |= !isfinite(p[k]);
     if (!bad) bad = !(fabs(p[2]) < g->snp_max);
@@ -1152,8 +1194,8 @@ static void refit_one(const ocfg *g, int64_t i, int64_t n, const double *ip, con
                 if (!propagate(p, C, &x, xl, g, NULL, NULL)) { status |= ST_STOP_SNP; break; }
             }
             if (status & (ST_STOP_SNP | ST_ROT_FAIL)) break;
-            int32_t j = idx[l * n + i];
-            if (j >= 0 && j < n_tkl) {
+            int32_t j = refit_index(idx[l * n + i], l, n_tkl, kdr);
+            if (j >= 0) {
                 const int det = (int)(kdr[j] >> 5), st = det / (NSTK * NLAY);
                 int ok = 1;
                 if (st != sec) {

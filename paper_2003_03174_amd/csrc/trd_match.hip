@@ -910,6 +910,8 @@ __device__ __forceinline__ bool match_lane(const DevCfg<TS> &g, const MatchIO &i
                 if (rc == 2 && kQueueNotPD) return false;
                 if (rc != 0 && (status & kStopSnp)) live = false;
             }
+        } else if (kQueueNotPD && (status & kNotPD)) {
+            return false;  // the float innovation covariance is not positive definite
         }
         write_layer(io, i, l, acc);
     }
@@ -1033,10 +1035,15 @@ __global__ void __launch_bounds__(256) k_match_coop(DevCfg<float> g, MatchIO io)
             R.glo = 1;
             R.ghi = 0;
             if (live) {
-                if (!predict(T, l, g, status))
+                if (!predict(T, l, g, status)) {
                     live = false;
-                else
+                } else {
                     search = open_road(T, l, grp, g, status, R);
+                    if (!search && kFloatCov && (status & kNotPD)) {
+                        queued = true;  // float innovation covariance not positive definite
+                        live = false;
+                    }
+                }
             }
             roads[tid] = R;
         }
@@ -1289,6 +1296,14 @@ __device__ __forceinline__ bool beam_track(const DevCfg<TS> &g, const MatchIO &i
                 if (open_road(H.T, l, grp, g, H.status, R)) scan_road_flat(R, g, io, L);
             }
         }
+        if (kQueueNotPD) {
+            // a float innovation covariance that is not positive definite
+            // sends the whole track to the double re-run
+            int lost = (H.status & kNotPD) ? 1 : 0;
+#pragma unroll
+            for (int off = N / 2; off >= 1; off >>= 1) lost |= __shfl_xor(lost, off, 64);
+            if (lost) return false;
+        }
         // survivors: N rounds of a group-wide minimum; a layer whose
         // predicted point lies in an empty chamber slot costs no penalty
         const TS skip_cost = H.cost + (no_chamber ? TS(0) : g.chi2_penalty);
@@ -1466,11 +1481,21 @@ __global__ void __launch_bounds__(256, sizeof(TS) == 4 ? 3 : 1) k_refit(DevCfg<T
     T.C[SS] = io.cov0[2];
     T.C[TT] = io.cov0[3];
     T.C[CC] = io.cov0[4];
+    // a usable index names a tracklet of that layer's chamber: in [0, n_tkl),
+    // with a chamber below 540 whose layer is l; any other counts as absent
+    // (so dx[det] is never read out of its table)
     int idx[kLayers], nm = 0;
 #pragma unroll
     for (int l = 0; l < kLayers; l++) {
-        idx[l] = io.idx[l * n + i];
-        nm += (idx[l] >= 0 && idx[l] < io.n_tkl) ? 1 : 0;
+        int j = io.idx[l * n + i];
+        if (j >= 0 && j < io.n_tkl) {
+            const uint32_t det = io.det_row[j] >> 5;
+            if (!(det < (uint32_t)kDet && det % kLayers == (uint32_t)l)) j = -1;
+        } else {
+            j = -1;
+        }
+        idx[l] = j;
+        nm += j >= 0 ? 1 : 0;
     }
     uint32_t status = 0;
     int nused = 0;
@@ -1488,7 +1513,7 @@ __global__ void __launch_bounds__(256, sizeof(TS) == 4 ? 3 : 1) k_refit(DevCfg<T
         for (int l = kLayers - 1; l >= 0; l--) {
             if (!reach_plane(T, l, g, status)) break;
             const int j = idx[l];
-            if (j >= 0 && j < io.n_tkl) {
+            if (j >= 0) {
                 const int det = (int)(io.det_row[j] >> 5), st = det / (kStacks * kLayers);
                 bool use = true;
                 if (st != T.sec) {

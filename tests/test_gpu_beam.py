@@ -43,11 +43,10 @@ def test_small_frame(prec, n_hyp):
     w = workload("c1_small_fp64")
     P = beam_params(w["params"], n_hyp, penalty=None if n_hyp == 1 else 9.0)
     got = run(w, P, prec)
-    ref = O.match(P, w, threads=0, margins=pu.MARGINS[prec])
-    rep = pu.compare(ref, got, prec)
+    ref = O.match(P, w, threads=0, margins=pu.BEAM_MARGINS[prec])
+    rep = pu.compare(ref, got, prec, max_flag_share=pu.MAX_FLAG_SHARE_BEAM)
     print(rep.summary())
     assert rep.ok, rep.summary()
-    assert rep.n_flagged <= 0.15 * rep.n
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -56,11 +55,10 @@ def test_frame_20k_four_hypotheses(prec):
     P = beam_params(w["params"], 4, penalty=9.0)
     got = run(w, P, prec)
     sel = np.arange(0, w["n_tracks"], 4)
-    ref = O.match(P, w, threads=0, margins=pu.MARGINS[prec], track_slice=sel)
-    rep = pu.compare(ref, got, prec, sel=sel)
+    ref = O.match(P, w, threads=0, margins=pu.BEAM_MARGINS[prec], track_slice=sel)
+    rep = pu.compare(ref, got, prec, sel=sel, max_flag_share=pu.MAX_FLAG_SHARE_BEAM)
     print(rep.summary())
     assert rep.ok, rep.summary()
-    assert rep.n_flagged <= 0.15 * rep.n
 
 
 def test_distortion_batch_sampled():
@@ -70,8 +68,8 @@ def test_distortion_batch_sampled():
     P = beam_params(w["params"], 4, penalty=9.0)
     got = run(w, P, "fp32")
     sel = np.sort(np.random.default_rng(11).choice(w["n_tracks"], 1500, replace=False))
-    ref = O.match(P, w, threads=0, margins=pu.MARGINS["fp32"], track_slice=sel)
-    rep = pu.compare(ref, got, "fp32", sel=sel)
+    ref = O.match(P, w, threads=0, margins=pu.BEAM_MARGINS["fp32"], track_slice=sel)
+    rep = pu.compare(ref, got, "fp32", sel=sel, max_flag_share=pu.MAX_FLAG_SHARE_BEAM_WIDE)
     print(rep.summary())
     assert rep.ok, rep.summary()
 

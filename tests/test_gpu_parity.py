@@ -94,14 +94,10 @@ def test_deflection_bins(prec, tilt):
     res = run_gpu(w, prec)
     check_binning(w, res)
     ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS[prec])
-    # Float state with tilted pads: on steep low-pT tracks the slope rounding
-    # reaches y through dx/f^3 (~50 cm per layer) and the tilt term feeds the
-    # y error into tan(lambda) through the gain; measured worst track 1.4e-5,
-    # 99.9 % of tracks within 1.1e-5 (in both float paths: the state, not the
-    # covariance, carries it).
-    loose = (tilt and prec != "fp64")
-    rep = pu.compare(ref, res, prec, state_tol_max=2e-5 if loose else None,
-                     q999_tol=1.5e-5 if loose else None)
+    # Float state with tilted pads: the bound of pu.tilted_float_tol (the
+    # float y's unit roundoff carried into z by the update's tilt gain)
+    tol = pu.tilted_float_tol(w["params"]) if (tilt and prec != "fp64") else None
+    rep = pu.compare(ref, res, prec, state_tol_max=tol, q999_tol=tol)
     print(rep.summary())
     assert rep.ok, rep.summary()
 
@@ -232,8 +228,10 @@ def test_empty_and_single():
         w1[k] = np.ascontiguousarray(w[k][5:6])
     w1["n_tracks"] = 1
     res = run_gpu(w1, "fp64")
-    ref = O.match(w1["params"], w1, threads=0)
-    assert pu.compare(ref, res, "fp64").ok
+    ref = O.match(w1["params"], w1, threads=0, margins=pu.MARGINS["fp64"])
+    # one track: the share bound is no statement here (a flagged track is
+    # still compared on the layers before its flag)
+    assert pu.compare(ref, res, "fp64", max_flag_share=1.0).ok
 
 
 def test_invalid_tracklets_and_bad_seeds():

@@ -97,12 +97,19 @@ def test_refit_few_and_bad():
         idx = idx.clone()
         idx[:3, ::2] = -1
         idx[0, 1] = 10 ** 8       # out of range: not a tracklet
+        # another layer's tracklet (its chamber exists, in range): absent here
+        idx[4, 1::4] = idx[5, 1::4]
         return idx
 
     matched, got = gpu_match_refit(w, "fp32", idx_edit=edit)
     ref = O.refit(w["params"], matched, matched["idx"], w)
     compare(ref, got, "fp32")
-    few = ((matched["idx"] >= 0) & (matched["idx"] < w["n_tracklets"])).sum(axis=0) < 4
+    ix = matched["idx"]
+    inr = (ix >= 0) & (ix < w["n_tracklets"])
+    det = np.where(inr, w["tkl_det_row"][np.clip(ix, 0, w["n_tracklets"] - 1)] >> 5, -1)
+    usable = inr & (det % 6 == np.arange(6)[:, None])
+    assert (inr & ~usable).sum() > 50
+    few = usable.sum(axis=0) < 4
     assert few.sum() > 100
     assert np.all(got["status"][few] & B.TRK_REFIT_FEW)
     assert np.array_equal(got["p"][:, few], matched["p"][:, few])

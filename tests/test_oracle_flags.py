@@ -219,3 +219,39 @@ def test_float_margins_add_their_absolute_terms():
         ry = math.sqrt(syy * (c2max - e_c2 - 6.25))
         cases.append(Case(f"chi2 {frac}", [(ry, 2.5 * math.sqrt(szz), 0.0)], fp, True, kind=CUT))
     _check(P, cases, m)
+
+
+def test_state_tolerance_margin_scales_with_the_road():
+    """The chi2 margins carry the compared path's state tolerance through
+    each road: with y, z errors up to m_state * max(|y|, 10 cm) (here, at
+    y = 0, z = 4 cm, no tilt or misalignment: 10 m_state each) a chi2 moves
+    by at most kchi sqrt(chi2) + kchi^2 / 4 with kchi = 2 |e| /
+    sqrt(lambda_min(S)) = 2 sqrt(2) 10 m_state / sqrt(min(S_yy, S_zz)) for
+    this diagonal S.  A near tie or a chi2-cut decision within that (plus
+    1e-4 relative) fires, one at 1.5 times the distance not."""
+    ms = 1e-4     # large enough that the road term dominates the relative one
+    m = dict(margin_rel=1e-4, m_state=ms)
+    P = _params(n_sigma_road=6.0)
+    syy, szz, _, _, _ = _road(P)
+    c2max = P["chi2_max"]
+    kchi = 2.0 * math.sqrt(2.0) * 10.0 * ms / math.sqrt(min(syy, szz))
+
+    def err(c2):
+        return kchi * math.sqrt(c2) + 0.25 * kchi * kchi
+
+    assert err(c2max) > 20 * 1e-4 * c2max
+    cases = []
+    for frac, fp in ((0.6, True), (1.5, False)):
+        # near tie: winner at chi2 2, runner-up above it by frac of the margin
+        c_w = 2.0
+        d = frac * (1e-4 * c_w + err(c_w) + err(c_w + 0.2))
+        cases.append(Case(f"tie {frac}", [(math.sqrt(c_w * syy), 0.0, 0.0),
+                                          (-math.sqrt((c_w + d) * syy), 0.0, 0.0)], P3 if fp else 0, True))
+        # chi2 cut: a lone winner just inside the cut
+        e_c2 = frac * (1e-4 * c2max + err(c2max))
+        ry = math.sqrt(syy * (c2max - e_c2 - 1.0))
+        cases.append(Case(f"cut {frac}", [(ry, math.sqrt(szz), 0.0)], P1 if fp else 0, True, kind=CUT))
+    _check(P, cases, m)
+    # without the state tolerance the same decisions lie outside the margin
+    quiet = [Case(c.name, c.cands, 0, True) for c in cases]
+    _check(P, quiet, dict(margin_rel=1e-4))

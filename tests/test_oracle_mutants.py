@@ -58,10 +58,15 @@ MUTANTS = {
     "update_width_at_the_minimum": ("double syu = poly2(g->sigma_y, p[2]);", "double syu = g->sigma_y[0];"),
     "flag_margin_wider": ("return fabs(a - lim) <= rel * fabs(lim) + abs_;",
                           "return fabs(a - lim) <= 4.0 * rel * fabs(lim) + abs_;"),
-    "flag_p2_any_loser": ("if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2)\n", "if (1)\n"),
+    "flag_p2_any_loser": ("if (best < 0 || c2 <= bchi + g->m_rel * bchi + g->m_chi2 + chi2_err(&r, bchi) + chi2_err(&r, c2))",
+                          "if (1)"),
     "flag_p2_two_gates": ("if (!fail || popcount4(fail) != 1 || !(fail & nm)) continue;",
                           "if (!fail || !(fail & nm)) continue;"),
-    "flag_p3_dropped": ("if (second - bchi <= g->m_rel * bchi + g->m_chi2) lf |= FL_P3;", ""),
+    "flag_p3_dropped": ("                    lf |= FL_P3;\n", "\n"),
+    "flag_margin_road_ignored": ("r->kchi = lmin > 0.0 ? 2.0 * sqrt(ey * ey + ez * ez) / sqrt(lmin) : INFINITY;",
+                                 "r->kchi = 0.0;"),
+    "flag_margin_largest_eigenvalue": ("const double lmin = 0.5 * (Syy + Szz) - sqrt(h * h + Syz * Syz);",
+                                       "const double lmin = 0.5 * (Syy + Szz) + sqrt(h * h + Syz * Syz);"),
     "flag_p1_dropped": ("if (bnear) lf |= FL_P1;", ""),
 }
 

@@ -119,3 +119,32 @@ def test_too_few_tracklets_are_copied():
     assert np.all((r["status"][few] & 64) != 0)
     assert np.array_equal(r["p"][:, few], m["p"][:, few])
     assert np.all(r["n_used"][few] == 0)
+
+
+def test_indices_that_name_no_tracklet_of_the_layer_are_absent():
+    """An index out of range, one whose chamber field is beyond the 540 slots,
+    or one naming another layer's tracklet is not that layer's tracklet: the
+    refit equals the one with -1 there."""
+    P, w = _frame(23, 200)
+    m = O.match(P, w, threads=0)
+    w2 = dict(w)
+    dr = w["tkl_det_row"].copy()
+    ntk = dr.size
+    bogus = ntk
+    dr = np.concatenate([dr, np.array([(600 << 5) | 3, ((2 ** 27 - 1) << 5) | 1], np.uint32)])
+    w2["tkl_det_row"] = dr
+    for k in ("tkl_y", "tkl_z", "tkl_dy"):
+        w2[k] = np.concatenate([w[k], [1.0, 2.0]])
+    idx = m["idx"].copy()
+    clean = idx.copy()
+    idx[0, 0::5] = bogus            # chamber 600: none
+    idx[1, 1::5] = bogus + 1        # chamber 2^27 - 1: none
+    idx[2, 2::5] = 10 ** 7          # out of range
+    idx[3, 3::5] = idx[4, 3::5]     # layer 4's tracklet given for layer 3
+    for l, s in ((0, 0), (1, 1), (2, 2), (3, 3)):
+        clean[l, s::5] = -1
+    r = O.refit(P, dict(p=m["p"], x=m["x"], sector=m["sector"]), idx, w2)
+    c = O.refit(P, dict(p=m["p"], x=m["x"], sector=m["sector"]), clean, w2)
+    for k in ("p", "cov", "x", "sector", "chi2", "n_used", "status"):
+        assert np.array_equal(r[k], c[k]), k
+    assert (c["n_used"] < m["n_match"]).sum() > 50
