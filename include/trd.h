@@ -23,8 +23,12 @@
  *     independent of each other.
  *   - Calls return an int status (TRD_OK or a negative TRD_E* code) and never
  *     throw across the ABI.  Invalid arguments are reported synchronously
- *     (TRD_EINVAL).  A HIP error raised by enqueued work is reported as
- *     TRD_EDEVICE by the next call on the context.  Per-track problems never
+ *     (TRD_EINVAL).  Before it enqueues anything, every stream-ordered call
+ *     checks for a HIP error left pending on the calling thread (a failed
+ *     launch or call) and for one that work already on its stream ran into
+ *     (a fault in an enqueued kernel, seen once the stream has reached it;
+ *     not checked while the stream is being captured); it consumes the error
+ *     and returns TRD_EDEVICE without enqueuing.  Per-track problems never
  *     fail a call: they are status bits (TRD_TRK_*).
  */
 #ifndef TRD_H
@@ -200,9 +204,15 @@ typedef struct trd_binning_view {
     int64_t n_tracklets;     /* tracklets passed to the last load */
 } trd_binning_view;
 
-/* Validates the config, selects `device` and uploads the geometry.
- * Errors: TRD_EINVAL (bad config), TRD_ENOMEM, TRD_EDEVICE.  On success *out
- * owns the context until trd_destroy. */
+/* Sets up the detector of Sect. 3 of the paper (18 sectors x 5 stacks x 6
+ * layers of chambers with pad rows, tilted pads, resolutions as polynomials
+ * in sin phi, the chi2 and dy cuts of the search) from the plain values of
+ * `cfg`: validates them, selects `device` and uploads the geometry.  Owns no
+ * tracklets yet.  Synchronous.  Errors: TRD_EINVAL (bad config: a field out
+ * of range, a bin width that is not a power of two, pad rows that do not tile
+ * [z_min, -z_min]), TRD_ENOMEM, TRD_EDEVICE (no such device, upload failed).
+ * On success *out owns the context until trd_destroy; on failure *out is
+ * NULL and nothing is held. */
 int trd_create(const trd_config *cfg, int device, trd_ctx **out);
 
 /* Reserves device buffers for up to `max_tracklets` tracklets, `max_groups`
@@ -211,11 +221,13 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out);
  * Errors: TRD_EINVAL, TRD_ENOMEM, TRD_EBUDGET. */
 int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t max_tracks);
 
-/* Bins the tracklets into (group, chamber, dy bin, y bin, pad row) cells
- * (pad rows innermost, so the cells of one (dy bin, y bin) that overlap a
- * road are contiguous): exact cell keys, a stable sort by (cell, input
- * index) into ctx-owned
- * sorted storage.  The caller may reuse `t`'s buffers once the stream has
+/* Prepares the search of Sect. 3 of the paper ("all tracklets inside a
+ * search road based on the covariance matrices", only tracklets of the same
+ * interaction, Sect. 4): bins the tracklets into (group, chamber, dy bin,
+ * y bin, pad row) cells (pad rows innermost, so the cells of one (dy bin,
+ * y bin) that overlap a road are contiguous): exact cell keys, a stable sort
+ * by (cell, input index) into ctx-owned sorted storage, which replaces the
+ * previous load's.  Stream-ordered.  The caller may reuse `t`'s buffers once the stream has
  * passed this call.  Tracklets with a det >= 540, a row >= n_rows, a group
  * outside [0, n_groups) or a non-finite value are dropped.
  * Errors: TRD_EINVAL (n < 0, n_groups < 1, NULL pointers with n > 0,
@@ -258,8 +270,10 @@ typedef struct trd_refit_out {
  * neighbour (else REFIT_SKIP), the step to its radius and the Kalman update,
  * then the layer's scattering (not below layer 0).  The covariance is kept in
  * double in every precision.  tkl: the tracklets the indices refer to (y, z,
- * det_row of the trd_match input, n_tkl of them; group unused).  Tracks with
- * fewer than refit_min valid indices are copied with REFIT_FEW, rejected
+ * det_row of the trd_match input, n_tkl of them; group unused).  An index
+ * counts only if it lies in [0, n_tkl) and names a tracklet of that layer's
+ * chamber (det < 540, det mod 6 = layer); others count as -1.  Tracks with
+ * fewer than refit_min usable indices are copied with REFIT_FEW, rejected
  * states with BAD_INPUT.  Stream-ordered.  Errors: TRD_EINVAL, TRD_EDEVICE. */
 int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, int64_t n_tkl, int64_t n,
               trd_refit_out *out, void *hip_stream);
@@ -326,10 +340,15 @@ int64_t trd_device_bytes(const trd_ctx *ctx);
  * captured into a graph. */
 int trd_kernel_times(trd_ctx *ctx, float *ms, int32_t max_n);
 
-/* Frees everything the context owns.  Waits for its device work. NULL is a no-op. */
+/* Ends the context of trd_create: frees every device buffer it owns (the
+ * sorted tracklets of the last load included, so views from
+ * trd_get_binning become invalid) and its events.  Waits for the device to
+ * finish its work first.  NULL is a no-op.  Never fails. */
 void trd_destroy(trd_ctx *ctx);
 
-/* Static text for a call status code. */
+/* Static text for a call status code (TRD_OK, TRD_E*): the name of the
+ * failure, for logs; "unknown status" for any other value.  The pointer is
+ * owned by the library and valid for its lifetime.  Needs no device. */
 const char *trd_status_string(int code);
 
 #ifdef __cplusplus

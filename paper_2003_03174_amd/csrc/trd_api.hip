@@ -330,6 +330,34 @@ int launch_status()
     return e == hipSuccess ? TRD_OK : TRD_EDEVICE;
 }
 
+// Errors left by earlier work, reported before anything is enqueued: the
+// calling thread's pending HIP error (a failed launch or call), then an
+// error that work already on the stream ran into (a fault in an enqueued
+// kernel surfaces there once the stream reaches it).  A stream being
+// captured into a graph is not queried (that would end the capture).
+// Either error is consumed and reported as TRD_EDEVICE.
+int pending_status(hipStream_t s)
+{
+    if (hipPeekAtLastError() != hipSuccess) {
+        (void)hipGetLastError();
+        return TRD_EDEVICE;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return TRD_EDEVICE;
+    }
+    if (cs == hipStreamCaptureStatusNone) {
+        const hipError_t e = hipStreamQuery(s);
+        // the query may record "not ready" as the thread's last error: clear
+        // it either way so that the launch check after this call sees only
+        // its own launches
+        (void)hipGetLastError();
+        if (e != hipSuccess && e != hipErrorNotReady) return TRD_EDEVICE;
+    }
+    return TRD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -408,9 +436,10 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
     const int64_t nc = n_cells_of(ctx->cfg, n_groups);
     if (nc >= (int64_t)UINT32_MAX - 1) return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
-    int rc;
-    if ((rc = ensure_tkl(ctx, n)) || (rc = ensure_cells(ctx, nc))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
+    int rc;
+    if ((rc = pending_status(s))) return rc;
+    if ((rc = ensure_tkl(ctx, n)) || (rc = ensure_cells(ctx, nc))) return rc;
     BinCfg b = ctx->gd.bin;
     b.n_groups = n_groups;
     b.n_cells = (uint32_t)nc;
@@ -445,6 +474,8 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
         return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
     int rc;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = pending_status(s))) return rc;
     const bool ord = ordered(ctx->cfg) && ctx->n_groups < kMaxOrderGroups;
     if ((ctx->cfg.precision == TRD_PREC_FP32 || ordered(ctx->cfg)) && (rc = ensure_trk(ctx, n))) return rc;
     MatchIO io{};
@@ -471,7 +502,6 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
     io.work_next = ctx->d_small + 2;
     io.work_done = ctx->d_small + 3;
-    const hipStream_t s = (hipStream_t)hip_stream;
     if (ctx->cfg.flags & TRD_CFG_TIME_KERNEL) {
         const int slot = (int)(ctx->ev_count % trd_ctx::kEvRing);
         io.ev_begin = ctx->ev[slot][0];
@@ -504,6 +534,7 @@ int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, in
         return TRD_EINVAL;
     if (n_tkl > 0 && (!tkl->y || !tkl->z || !tkl->det_row)) return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    if (int rc = pending_status((hipStream_t)hip_stream)) return rc;
     RefitIO io{};
     io.ip = in->p;
     io.ix = in->x;
@@ -535,6 +566,7 @@ int trd_residual_sums(trd_ctx *ctx, const trd_reference *ref, const trd_tpc_clus
     if (!ref->p || !ref->x || !ref->sector || !ref->status || !cl->first) return TRD_EINVAL;
     if (n_cl > 0 && (!cl->y || !cl->z || !cl->row_sec)) return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    if (int rc = pending_status((hipStream_t)hip_stream)) return rc;
     const trd_config &c = ctx->cfg;
     ResidualIO io{};
     io.rp = ref->p;
@@ -562,6 +594,7 @@ int trd_voxel_solve(trd_ctx *ctx, const double *sums, float *dist, void *hip_str
 {
     if (!ctx || !sums || !dist) return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    if (int rc = pending_status((hipStream_t)hip_stream)) return rc;
     const trd_config &c = ctx->cfg;
     launch_voxel_solve(sums, TRD_N_SECTORS * c.vox_nx * c.vox_ny * c.vox_nz, c.vox_min, dist,
                        (hipStream_t)hip_stream);
@@ -587,6 +620,7 @@ int trd_copy_binning(trd_ctx *ctx, uint32_t *offsets_out, float *sorted_out, int
     if (max_valid < ctx->n_tkl) return TRD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (int rc = pending_status(s)) return rc;
     if (hipMemcpyAsync(offsets_out, ctx->d_offsets, sizeof(uint32_t) * (size_t)(ctx->n_cells + 1),
                        hipMemcpyDeviceToDevice, s) != hipSuccess)
         return TRD_EDEVICE;

@@ -128,7 +128,7 @@ void launch_refit(int precision, const DevCfg<double> &gd, const DevCfg<float> &
 // Residual maps: reference tracks, TPC clusters, voxel sums (see
 // trd_residual_sums in the public header).
 constexpr int kVoxelSums = 8;
-constexpr int kMaxVoxels = 2048;  // the per-workgroup LDS copy of the sums: 64 KB
+constexpr int kMaxVoxels = 2048;  // the per-workgroup LDS copy of the sums: 64 KB (float), 128 KB (double)
 struct ResidualIO {
     const void *rp, *rx;
     const int32_t *rsec;

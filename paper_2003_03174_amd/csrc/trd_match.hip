@@ -1621,8 +1621,9 @@ __device__ __forceinline__ bool turn_state(TS &x, TS &y, TS &s, bool up, const D
 }
 
 // One lane per reference track, walking its clusters inward.  The 8 sums of
-// every voxel are kept per workgroup in LDS (float) and added to the global
-// double sums at the end; a lane keeps the sums of the voxel it is in in
+// every voxel are kept per workgroup in LDS, in the state type (float, or
+// double for the double path: 64 B per voxel, at most 128 KB), and added to
+// the global double sums at the end; a lane keeps the sums of the voxel it is in in
 // registers and adds them to LDS only when the walk leaves that voxel (a
 // track stays in one voxel for several pad rows), which cuts the LDS atomics
 // several-fold.  The clusters of a track are fetched kPre at a time ahead of
@@ -1631,25 +1632,26 @@ template <typename TS, int kThreads>
 __global__ void __launch_bounds__(kThreads) k_residual_sums(DevCfg<TS> g, ResidualIO io)
 {
     constexpr int kPre = 8;
-    extern __shared__ float ls[];
+    extern __shared__ __align__(8) unsigned char lds_raw[];
+    TS *ls = reinterpret_cast<TS *>(lds_raw);
     const int nsum = io.nvox * kVoxelSums;
-    for (int k = threadIdx.x; k < nsum; k += blockDim.x) ls[k] = 0.f;
+    for (int k = threadIdx.x; k < nsum; k += blockDim.x) ls[k] = TS(0);
     __syncthreads();
     const TS *rp = reinterpret_cast<const TS *>(io.rp);
     const TS *rx = reinterpret_cast<const TS *>(io.rx);
     const TS step = TS(io.x_out - io.x_in) / TS(io.n_rows - 1);
     const TS fxs = TS(io.nx) / TS(io.x_out - io.x_in);
     int vox = -1;  // voxel whose sums the lane holds
-    float acc[kVoxelSums];
+    TS acc[kVoxelSums];
 #pragma unroll
-    for (int q = 0; q < kVoxelSums; q++) acc[q] = 0.f;
+    for (int q = 0; q < kVoxelSums; q++) acc[q] = TS(0);
     auto flush = [&]() {
         if (vox >= 0) {
-            float *S = ls + kVoxelSums * vox;
+            TS *S = ls + kVoxelSums * vox;
 #pragma unroll
             for (int q = 0; q < kVoxelSums; q++) {
                 atomicAdd(&S[q], acc[q]);
-                acc[q] = 0.f;
+                acc[q] = TS(0);
             }
         }
     };
@@ -1709,22 +1711,22 @@ __global__ void __launch_bounds__(kThreads) k_residual_sums(DevCfg<TS> g, Residu
                     flush();
                     vox = v;
                 }
-                acc[0] += 1.f;
-                acc[1] += float(ty);
-                acc[2] += float(tz);
-                acc[3] += float(ty * ty + tz * tz);
-                acc[4] += float(ry);
-                acc[5] += float(rz);
-                acc[6] += float(ty * ry + tz * rz);
-                acc[7] += float(ry * ry + rz * rz);
+                acc[0] += TS(1);
+                acc[1] += ty;
+                acc[2] += tz;
+                acc[3] += ty * ty + tz * tz;
+                acc[4] += ry;
+                acc[5] += rz;
+                acc[6] += ty * ry + tz * rz;
+                acc[7] += ry * ry + rz * rz;
             }
         }
     }
     flush();
     __syncthreads();
     for (int k = threadIdx.x; k < nsum; k += blockDim.x) {
-        const float v = ls[k];
-        if (v != 0.f) atomicAdd(&io.sums[k], (double)v);
+        const TS v = ls[k];
+        if (v != TS(0)) atomicAdd(&io.sums[k], (double)v);
     }
 }
 
@@ -1859,14 +1861,17 @@ void launch_residual_sums(int precision, const DevCfg<double> &gd, const DevCfg<
 {
     if (io.n <= 0) return;
     constexpr int kThreads = 1024;
-    const size_t lds = sizeof(float) * (size_t)io.nvox * kVoxelSums;
+    const size_t lds = (precision == 0 ? sizeof(double) : sizeof(float)) * (size_t)io.nvox * kVoxelSums;
     int64_t blocks = (io.n + kThreads - 1) / kThreads;
-    const int64_t cap = 2 * (int64_t)(n_cu > 0 ? n_cu : 1);
+    // two workgroups per CU (one with the double sums: up to 128 KB of LDS)
+    const int64_t cap = (precision == 0 ? 1 : 2) * (int64_t)(n_cu > 0 ? n_cu : 1);
     if (blocks > cap) blocks = cap;
-    if (precision == 0)
+    if (precision == 0) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_residual_sums<double, kThreads>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((k_residual_sums<double, kThreads>), dim3((unsigned)blocks), dim3(kThreads), lds, s, gd,
                            io);
-    else
+    } else
         hipLaunchKernelGGL((k_residual_sums<float, kThreads>), dim3((unsigned)blocks), dim3(kThreads), lds, s, gf,
                            io);
 }

@@ -338,3 +338,27 @@ def test_kernel_times():
     with pytest.raises(B.TrdError):
         m.kernel_times()
     m.close()
+
+
+def test_pending_hip_error_is_reported_by_the_next_call():
+    """A HIP error left pending on the calling thread (here a failed
+    hipSetDevice, which touches no device memory) makes the next call return
+    TRD_EDEVICE without enqueuing anything; the error is consumed, so the
+    call after it runs normally and gives the usual result."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    w = workload("c1_small_fp64")
+    base = run_gpu(w, "fp32")
+    d = B.device_inputs(synth.to_device_layout(w), "fp32")
+    m = B.Matcher(w["params"], "fp32")
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+    torch.cuda.synchronize()
+    assert hip.hipSetDevice(ctypes.c_int(1 << 20)) != 0
+    with pytest.raises(B.TrdError) as e:
+        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    assert e.value.code == B.TRD_EDEVICE
+    out = pu.to_numpy(m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"]))
+    torch.cuda.synchronize()
+    m.close()
+    for k in ("idx", "p", "cov", "status"):
+        assert np.array_equal(out[k], base[k], equal_nan=True), k

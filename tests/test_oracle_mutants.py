@@ -62,7 +62,7 @@ MUTANTS = {
                           "if (1)"),
     "flag_p2_two_gates": ("if (!fail || popcount4(fail) != 1 || !(fail & nm)) continue;",
                           "if (!fail || !(fail & nm)) continue;"),
-    "flag_p3_dropped": ("                    lf |= FL_P3;\n", "\n"),
+    "flag_p3_dropped": ("                    lf |= FL_P3;\n", "                    ;\n"),
     "flag_margin_road_ignored": ("r->kchi = lmin > 0.0 ? 2.0 * sqrt(ey * ey + ez * ez) / sqrt(lmin) : INFINITY;",
                                  "r->kchi = 0.0;"),
     "flag_margin_largest_eigenvalue": ("const double lmin = 0.5 * (Syy + Szz) - sqrt(h * h + Syz * Syz);",
