@@ -242,6 +242,22 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
  * TRD_ENOMEM, TRD_EBUDGET, TRD_EDEVICE. */
 int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream);
 
+/* trd_match for callers that cannot allocate device memory: code under
+ * stream (graph) capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels and results as trd_match, bit for bit, with the
+ * tracks matched in the caller's order; it calls no allocating routine.  Its
+ * scratch (the float path's re-run queue and the kernels' counters) is one
+ * library-owned device array per GPU of 4 * (64 + 2^21) bytes (8 MB), held
+ * from the first trd_create on that GPU until the process ends; the counters
+ * are cleared by a fill kernel at the start of every call.  The caller still
+ * passes inputs and outputs, and the context must have been created (and its
+ * tracklets loaded, which allocates unless trd_reserve sized it) beforehand.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on the same GPU (other streams or threads, other contexts) race and give
+ * wrong results; serialise them.  Errors: as trd_match, and TRD_EINVAL for
+ * n > 2^21 tracks or a device ordinal >= 64. */
+int trd_match_noalloc(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream);
+
 /* Matched tracks for trd_refit (device arrays of the state type, as written
  * by trd_match). */
 typedef struct trd_refit_in {

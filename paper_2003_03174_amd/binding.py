@@ -34,7 +34,8 @@ TRD_CFG_INPUT_ORDER = 8
 TRD_CFG_TIME_KERNEL = 16
 
 # every symbol include/trd.h declares
-EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_refit", "trd_residual_sums",
+EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_match_noalloc", "trd_refit",
+           "trd_residual_sums",
            "trd_voxel_solve", "trd_get_binning", "trd_copy_binning", "trd_device_bytes", "trd_kernel_times",
            "trd_destroy", "trd_status_string")
 
@@ -120,6 +121,7 @@ def lib():
         L.trd_reserve.argtypes = [vp, C.c_int64, C.c_int32, C.c_int64]
         L.trd_load_tracklets.argtypes = [vp, C.POINTER(trd_tracklets), C.c_int64, C.c_int32, vp]
         L.trd_match.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
+        L.trd_match_noalloc.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
         L.trd_refit.argtypes = [vp, C.POINTER(trd_refit_in), C.POINTER(trd_tracklets), C.c_int64, C.c_int64,
                                 C.POINTER(trd_refit_out), vp]
         L.trd_residual_sums.argtypes = [vp, C.POINTER(trd_reference), C.POINTER(trd_tpc_clusters), C.c_int64,
@@ -210,6 +212,11 @@ def trd_load_tracklets(ctx, t: trd_tracklets, n, n_groups, stream=0):
 
 def trd_match(ctx, trk: trd_tracks, n, res: trd_results, stream=0):
     _check(lib().trd_match(ctx, C.byref(trk), int(n), C.byref(res), stream or None), "trd_match")
+
+
+def trd_match_noalloc(ctx, trk: trd_tracks, n, res: trd_results, stream=0):
+    _check(lib().trd_match_noalloc(ctx, C.byref(trk), int(n), C.byref(res), stream or None),
+           "trd_match_noalloc")
 
 
 def trd_refit(ctx, rin: trd_refit_in, tkl: trd_tracklets, n_tkl, n, rout: trd_refit_out, stream=0):
@@ -328,7 +335,9 @@ class Matcher:
             status=torch.empty(n, dtype=torch.int32, device=dev),
         )
 
-    def match(self, p, cov, x, sector, group=None, out=None, stream=None):
+    def match(self, p, cov, x, sector, group=None, out=None, stream=None, noalloc=False):
+        """trd_match (or trd_match_noalloc with `noalloc`) into `out` (a dict
+        of device tensors as alloc_results gives; allocated if None)."""
         n = int(x.numel())
         for t in (p, cov, x):
             assert t.is_cuda and t.is_contiguous() and t.dtype == self.fdtype
@@ -339,7 +348,7 @@ class Matcher:
                          group.data_ptr() if group is not None else None)
         res = trd_results(*(None if out[k] is None else out[k].data_ptr() for k in
                             ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status")))
-        trd_match(self.ctx, trk, n, res, _stream_handle(stream))
+        (trd_match_noalloc if noalloc else trd_match)(self.ctx, trk, n, res, _stream_handle(stream))
         return out
 
     def refit(self, matched, y, z, det_row, stream=None):

@@ -3,6 +3,7 @@
 // trd_load_tracklets and trd_match.  Nothing here synchronises the stream
 // except trd_reserve/trd_destroy (allocation, free).
 #include <math.h>
+#include <mutex>
 #include <new>
 #include <string.h>
 
@@ -50,6 +51,42 @@ struct trd_ctx {
 };
 
 namespace {
+
+// ---- scratch of trd_match_noalloc -----------------------------------------
+// One file-scope device array per GPU (each device holds its own copy while
+// the library is loaded): the float path's re-run queue and the four
+// counters of the match kernels.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in); trd_create takes its device
+// address once per device with hipGetSymbolAddress and every later use goes
+// through that address.
+constexpr int64_t kNoAllocMaxTracks = int64_t(1) << 21;  // 8 MB of queue
+constexpr int64_t kScratchHead = 64;                    // counters, padded to 256 bytes
+static __device__ __align__(256) uint32_t scratch[kScratchHead + kNoAllocMaxTracks];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Takes the device address of `scratch` on the current device `dev` once.
+int scratch_setup(int dev)
+{
+    if (dev >= kMaxScratchDevices) return TRD_OK;  // trd_match_noalloc then refuses this device
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return TRD_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return TRD_EDEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+    return TRD_OK;
+}
+
+uint32_t *scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 bool finite_all(const double *v, int n)
 {
@@ -375,6 +412,7 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out)
         return device < 0 ? TRD_EINVAL : TRD_EDEVICE;
     }
     if (hipSetDevice(device) != hipSuccess) return TRD_EDEVICE;
+    if ((rc = scratch_setup(device))) return rc;
     trd_ctx *ctx = new (std::nothrow) trd_ctx();
     if (!ctx) return TRD_ENOMEM;
     ctx->device = device;
@@ -463,7 +501,16 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
     return TRD_OK;
 }
 
-int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// The launch sequence of trd_match.  With `fixed` (trd_match_noalloc) the
+// re-run queue and the counters come from that scratch, the tracks are
+// matched in the caller's order and nothing is allocated; otherwise the
+// context's buffers are used (grown as needed).
+int match_impl(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream,
+               uint32_t *fixed)
 {
     if (!ctx || !in || !out || n < 0) return TRD_EINVAL;
     if (!ctx->loaded) return TRD_ESTATE;
@@ -476,8 +523,9 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     int rc;
     const hipStream_t s = (hipStream_t)hip_stream;
     if ((rc = pending_status(s))) return rc;
-    const bool ord = ordered(ctx->cfg) && ctx->n_groups < kMaxOrderGroups;
-    if ((ctx->cfg.precision == TRD_PREC_FP32 || ordered(ctx->cfg)) && (rc = ensure_trk(ctx, n))) return rc;
+    const bool ord = !fixed && ordered(ctx->cfg) && ctx->n_groups < kMaxOrderGroups;
+    if (!fixed && (ctx->cfg.precision == TRD_PREC_FP32 || ordered(ctx->cfg)) && (rc = ensure_trk(ctx, n)))
+        return rc;
     MatchIO io{};
     io.sorted = ctx->d_sorted;
     io.offsets = ctx->d_offsets;
@@ -496,12 +544,16 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
     io.ochi2l = out->chi2_layer;
     io.onm = out->n_match;
     io.ost = out->status;
-    io.fb_list = ctx->d_fb;
-    io.fb_count = ctx->d_small;
-    io.fb_done = ctx->d_small + 1;
+    uint32_t *counters = fixed ? fixed : ctx->d_small;
+    io.fb_list = fixed ? reinterpret_cast<int32_t *>(fixed + kScratchHead) : ctx->d_fb;
+    io.fb_count = counters;
+    io.fb_done = counters + 1;
     io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
-    io.work_next = ctx->d_small + 2;
-    io.work_done = ctx->d_small + 3;
+    io.work_next = counters + 2;
+    io.work_done = counters + 3;
+    // the shared scratch keeps the last call's contents: the counters start
+    // at zero (a fill kernel, also under stream capture)
+    if (fixed) launch_fill_u32(counters, 0u, 4, s);
     if (ctx->cfg.flags & TRD_CFG_TIME_KERNEL) {
         const int slot = (int)(ctx->ev_count % trd_ctx::kEvRing);
         io.ev_begin = ctx->ev[slot][0];
@@ -521,6 +573,24 @@ int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, v
                      (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu, s);
     if (ord) launch_order_out(ctx->cfg.precision, io, ord_buf, s);
     return launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+int trd_match(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream)
+{
+    return match_impl(ctx, in, n, out, hip_stream, nullptr);
+}
+
+int trd_match_noalloc(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream)
+{
+    if (!ctx) return TRD_EINVAL;
+    if (n > kNoAllocMaxTracks) return TRD_EINVAL;
+    uint32_t *sc = scratch_of(ctx->device);
+    if (!sc) return ctx->device >= kMaxScratchDevices ? TRD_EINVAL : TRD_EDEVICE;
+    return match_impl(ctx, in, n, out, hip_stream, sc);
 }
 
 int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, int64_t n_tkl, int64_t n,
