@@ -394,9 +394,10 @@ struct Best {
     float y, z; // its measurement
 
     // keeps a passing candidate if it is the lexicographic (chi2, index) minimum
+    // (bitwise, not short-circuit, logic: no branches in the record loop)
     __device__ __forceinline__ void offer(TS c, int oj, float yy, float zz, int st, bool pass)
     {
-        const bool take = pass && (c < chi2 || (c == chi2 && oj < idx));
+        const bool take = pass & ((c < chi2) | ((c == chi2) & (oj < idx)));
         chi2 = take ? c : chi2;
         idx = take ? oj : idx;
         stack = take ? st : stack;
@@ -705,9 +706,18 @@ __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<T
                                                A &B)
 {
     constexpr int kBatch = 4, kU = 4;
-    const RangeGrid q = range_grid(R, g.bin.n_rows);
+    const int nr = g.bin.n_rows;
+    const RangeGrid q = range_grid(R, nr);
     const bool shifted = g.dx_max != TS(0);
-    int is = 0, id = 0, iy = 0;
+    // Cell index of the first pad row of range (is, id, iy), kept as a running
+    // sum: one y bin further adds sy, the next dy bin (y back to the first)
+    // adds sy + wy, the next stack (dy and y back to the first) adds ws on top
+    // (additions only: no integer multiplies per range).
+    const uint32_t sy = (uint32_t)nr, sd = (uint32_t)g.bin.n_yb * sy, ss = (uint32_t)(kLayers * g.bin.n_db) * sd;
+    const uint32_t wy = sd - (uint32_t)q.ny * sy, ws = ss - (uint32_t)q.nd * sd;
+    uint32_t cur = ((((uint32_t)(R.gdet0 + q.s0 * kLayers)) * (uint32_t)g.bin.n_db + (uint32_t)R.db0) *
+                        (uint32_t)g.bin.n_yb + (uint32_t)R.yb0) * sy;
+    int is = 0, id = 0, iy = 0, so = q.s0 * nr;
     for (int j0 = 0; j0 < q.n; j0 += kBatch) {
         uint32_t a[kBatch], e[kBatch];
         int st[kBatch];
@@ -717,12 +727,19 @@ __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<T
             e[u] = 0;
             st[u] = q.s0 + is;
             if (j0 + u < q.n) {
-                range_bounds(R, g, io, st[u], id, iy, &a[u], &e[u]);
+                // the road's pad rows within this stack
+                const int r0 = max(R.glo - so, 0), r1 = min(R.ghi - so, nr - 1);
+                a[u] = io.offsets[cur + (uint32_t)r0];
+                e[u] = io.offsets[cur + (uint32_t)r1 + 1u];
+                cur += sy;
                 if (++iy == q.ny) {
                     iy = 0;
+                    cur += wy;
                     if (++id == q.nd) {
                         id = 0;
+                        cur += ws;
                         ++is;
+                        so += nr;
                     }
                 }
             }
@@ -750,14 +767,15 @@ __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<T
                     su[u] = in ? st[q] : su[u];
                 }
                 dxd[u] = TS(0);
+                // past the end: a record whose NaN position fails every gate
+                rec[u] = make_float4(__builtin_nanf(""), 0.f, 0.f, __int_as_float(0x7fffffff));
                 if (f < tot) {
                     rec[u] = io.sorted[k];
                     if (shifted) dxd[u] = g.dx[R.sdet0 + su[u] * kLayers];
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kU; u++)
-                if (f0 + (uint32_t)u < tot) gate_record(R, g, rec[u], su[u], dxd[u], B);
+            for (int u = 0; u < kU; u++) gate_record(R, g, rec[u], su[u], dxd[u], B);
         }
     }
 }
