@@ -176,8 +176,9 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
         torch.cuda.synchronize()
         if k:
             ref_ms.append(e0.elapsed_time(e1))
+    last = {k: (v.cpu().numpy() if v is not None else None) for k, v in full.items()}
     res = dict(wall_ms_per_step=1e3 * wall / steps, bin_ms=t_bin, match_ms=t_match, step_ms=t_step,
-               refit_ms=ref_ms,
+               refit_ms=ref_ms, result=last,
                kernel_ms=ktimes,
                n_fallback=int(((st & B.TRK_FP64_FALLBACK) != 0).sum()),
                n_ge2=int((nm >= 2).sum()))
@@ -191,9 +192,26 @@ def pct(v, q):
     return v[k]
 
 
-def cpu_baseline(w, budget_s=12.0):
+def cpu_model():
+    """The host CPU's model name and its logical core count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline(w, gpu=None, prec="fp32", budget_s=6.0, runs=3):
     """The FP64 oracle on the host cores: binning of all tracklets plus the
-    matching of a bounded sample of tracks, extrapolated to the batch."""
+    matching of a bounded sample of tracks, extrapolated to the batch (median
+    of `runs` runs).  With `gpu` (the device results of the whole batch) the
+    oracle's tracks of a 3,000-track sample also give the error of the device
+    path per quantity and the decision-margin flag counts."""
     import numpy as np
     from oracle import oracle as O
 
@@ -209,11 +227,14 @@ def cpu_baseline(w, budget_s=12.0):
     t_probe = max(time.perf_counter() - t0 - t_bin, 1e-6) / probe.size
     ns = int(min(n, max(probe.size, budget_s / t_probe)))
     sample = np.arange(0, n, max(1, n // ns))[:ns]
-    t0 = time.perf_counter()
-    O.match(P, w, threads=cores, track_slice=sample)
-    t_call = time.perf_counter() - t0
-    per_trk = max(t_call - t_bin, 1e-9) / sample.size
-    est = t_bin + per_trk * n
+    ests, calls = [], []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        O.match(P, w, threads=cores, track_slice=sample)
+        t_call = time.perf_counter() - t0
+        calls.append(t_call)
+        ests.append(t_bin + max(t_call - t_bin, 1e-9) / sample.size * n)
+    est = float(np.median(ests))
     # one thread: the binning and a smaller sample, same extrapolation
     s1 = np.arange(0, n, max(1, n // 20000))
     t0 = time.perf_counter()
@@ -223,11 +244,46 @@ def cpu_baseline(w, budget_s=12.0):
     O.bin_tracklets(P, w)
     t_bin1 = time.perf_counter() - t0   # the binning is single-threaded in the oracle
     est1 = t_bin1 + max(t_one - t_bin1, 1e-9) / s1.size * n
-    return dict(value=n / est, unit="tracks/s", cores=cores, kind="oracle",
-                value_1_thread=n / est1,
-                sample=(f"binning of all {w['n_tracklets']} tracklets ({t_bin:.2f} s) + matching of "
-                        f"{sample.size} of {n} tracks (every {max(1, n // ns)}th, {t_call - t_bin:.2f} s), "
-                        f"extrapolated to the whole batch; 1 thread: {s1.size} tracks"))
+    model, logical = cpu_model()
+    out = dict(value=n / est, unit="tracks/s", cores=cores, kind="oracle",
+               cpu_model=model, logical_cpus=logical,
+               runs=[n / e for e in ests],
+               value_1_thread=n / est1,
+               sample=(f"binning of all {w['n_tracklets']} tracklets ({t_bin:.2f} s) + matching of "
+                       f"{sample.size} of {n} tracks (every {max(1, n // ns)}th, median of {runs} runs, "
+                       f"{float(np.median(calls)) - t_bin:.2f} s), extrapolated to the whole batch; "
+                       f"1 thread: {s1.size} tracks"))
+    if gpu is not None:
+        out["parity"] = parity_sample(O, w, gpu, prec, cores)
+    return out
+
+
+def parity_sample(O, w, gpu, prec, cores, n_sample=3000):
+    """Error of the device results against the FP64 oracle on sampled tracks,
+    per quantity (relative, floors 10 cm, 10 cm, 0.1, 0.1, 0.1 c/GeV), and the
+    oracle's decision-margin flags (the exempt tracks)."""
+    import numpy as np
+    from tests import parity_util as pu
+
+    sel = np.sort(np.random.default_rng(0).choice(w["n_tracks"], min(n_sample, w["n_tracks"]),
+                                                  replace=False))
+    hyp = int(w["params"].get("n_hyp", 0)) > 0
+    margins = (pu.BEAM_MARGINS if hyp else pu.MARGINS)[prec]
+    ref = O.match(w["params"], w, threads=cores, margins=margins, track_slice=sel)
+    rep = pu.compare(ref, gpu, prec, sel=sel, max_flag_share=pu.MAX_FLAG_SHARE_BEAM_WIDE if hyp else None)
+    names = ("y", "z", "sin_phi", "tan_lambda", "q_over_pt")
+    return {
+        "n_sampled": int(sel.size),
+        "tolerance": {"state": pu.STATE_TOL[prec], "cov": pu.COV_TOL[prec], "chi2": pu.chi2_tol(prec)},
+        "max_rel_err": dict(zip(names, rep.state_err_by_comp)),
+        "max_rel_err_x": rep.x_err,
+        "max_cov_err": rep.cov_err,
+        "max_chi2_err": rep.chi2_err,
+        "idx_mismatch": rep.idx_mismatch + rep.idx_mismatch_flagged_prefix,
+        "status_mismatch": rep.status_mismatch,
+        "flagged": dict(rep.flag_counts, total=rep.n_flagged, near_chi2_cut_only=rep.n_flag_cut_only),
+        "ok": bool(rep.ok),
+    }
 
 
 def residual_bench(args):
@@ -493,6 +549,11 @@ def main():
         # of active lanes per instruction, from the committed counter summary
         "valu": profiled_valu() if traffic is not None else None,
     }
+    if line["valu"] is not None:
+        v = line["valu"]
+        line["roofline"]["binding"] = (f"VALU issue and lane divergence: {100 * v['issue_frac']:.0f} % of the "
+                                       f"issue slots, {100 * v['lane_frac']:.0f} % of the lanes active; HBM "
+                                       f"{100 * line['roofline']['frac']:.1f} % on algorithmic bytes")
     if not args.no_fp64 and args.precision != "fp64":
         log("timing the plain FP64 comparator")
         r64 = run_gpu(w, "fp64", max(3, args.steps // 2), 2)
@@ -501,7 +562,7 @@ def main():
                               "match_avg_ms": sum(r64["match_ms"]) / len(r64["match_ms"])}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(w)
+        line["cpu_baseline"] = cpu_baseline(w, gpu=r["result"], prec=args.precision)
     print(json.dumps(line), flush=True)
 
 

@@ -13,7 +13,8 @@ import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtrd.so")
+# TRD_LIB: another build of the same library (a sanitizer build in a CPU test)
+LIB_PATH = os.environ.get("TRD_LIB") or os.path.join(HERE, "libtrd.so")
 
 TRD_OK, TRD_EINVAL, TRD_ENOMEM, TRD_EDEVICE, TRD_ESTATE, TRD_EBUDGET = 0, -1, -2, -3, -4, -5
 TRD_PREC_FP64, TRD_PREC_FP32, TRD_PREC_FP32_COV64 = 0, 1, 2
