@@ -161,6 +161,19 @@ typedef struct trd_config {
                                  + layer).  Its tracklets are dropped at load; with n_hyp >= 1
                                  a layer whose predicted point lies in such a slot costs no
                                  chi2_penalty. */
+    /* Field inhomogeneity (Sect. 3: the precise extrapolation to a chamber
+       accounts for the field).  Bz(r, z) = bz (1 + field_br (r / 370 cm)^2 +
+       field_bz (z / 360 cm)^2), r the distance from the beam axis; both 0 =
+       uniform field (closed-form helix steps).  Otherwise every propagation
+       of the matching and the refit integrates y' = tan(phi), z' =
+       tan(lambda)/cos(phi), sin(phi)' = -kappa Bz q/pT over local x with the
+       classical 4th-order Runge-Kutta method in equal steps of at most
+       field_step, and transports the covariance with the exact helix
+       Jacobian over the whole step in the field the integration saw (the mean
+       of the Runge-Kutta weighted field samples).  The residual maps keep the
+       uniform-field step. */
+    double field_br, field_bz; /* |.| < 1 */
+    double field_step;        /* cm, in (0, 20]; used with a field map */
 } trd_config;
 
 /* Tracklets of one or more groups (device arrays of length n). */

@@ -43,6 +43,7 @@ class OCfg(C.Structure):
         ("eloss_xrho", C.c_double), ("eloss_za", C.c_double), ("eloss_i", C.c_double),
         ("absent", C.c_uint8 * 540), ("pad2_", C.c_uint8 * 4), ("m_ke", C.c_double),
         ("m_state", C.c_double),
+        ("field_br", C.c_double), ("field_bz", C.c_double), ("field_step", C.c_double),
     ]
 
 class OTpc(C.Structure):
@@ -135,6 +136,9 @@ def make_cfg(params, margin_rel=1e-4, m_len=0.0, m_dy=0.0, m_chi2=0.0, m_snp=0.0
     c.m_rel, c.m_len, c.m_dy, c.m_chi2, c.m_snp = margin_rel, m_len, m_dy, m_chi2, m_snp
     c.m_ke = m_ke
     c.m_state = m_state
+    c.field_br = float(P.get("field_br", 0.0))
+    c.field_bz = float(P.get("field_bz", 0.0))
+    c.field_step = float(P.get("field_step", 0.25))
     c.n_rows, c.n_yb = P["n_rows"], P["n_yb"]
     c.n_hyp = int(P.get("n_hyp", 0))
     c.chi2_penalty = float(P.get("chi2_penalty", P["chi2_max"]))

@@ -105,6 +105,11 @@ typedef struct {
     double m_state;             /* decision margin: relative tolerance of the compared
                                    path's predicted y and z (floor 10 cm), carried into
                                    each road's chi2 (0: none) */
+    /* field inhomogeneity (Sect. 3: the precise extrapolation accounts for the
+     * field): Bz(r, z) = bz (1 + field_br (r / 370 cm)^2 + field_bz (z / 360 cm)^2);
+     * both 0 = uniform field, stepped in closed form */
+    double field_br, field_bz;
+    double field_step;          /* largest x step of the integration in a field map, cm */
 } ocfg;
 
 static const double KAPPA = 2.99792458e-3;
@@ -191,19 +196,28 @@ static int near_lim(double a, double lim, double rel, double abs_)
 /* Moves the state from *x to x2 along the helix.  Returns 0 (state
  * untouched) if |sin phi| would reach snp_max.  J (optional) receives the
  * Jacobian d p(x2) / d p(x). */
-static int propagate(double p[5], double C[5][5], double *x, double x2,
-                     const ocfg *g, unsigned *flags, double Jout[5][5])
+/* Bz (T) at a point of the sector frame: the field depends on the radius
+ * r = sqrt(x^2 + y^2) (any frame) and on z. */
+#define FIELD_RREF 370.0
+#define FIELD_ZREF 360.0
+static int field_map(const ocfg *g) { return g->field_br != 0.0 || g->field_bz != 0.0; }
+static double field_at(const ocfg *g, double x, double y, double z)
 {
-    double dx = x2 - *x;
-    double k = -KAPPA * g->bz;            /* d curvature / d (q/pT) */
-    double cu = k * p[4];                 /* signed curvature, 1/cm */
-    double s1 = p[2];
+    const double r2 = x * x + y * y;
+    return g->bz * (1.0 + g->field_br * r2 / (FIELD_RREF * FIELD_RREF) + g->field_bz * z * z / (FIELD_ZREF * FIELD_ZREF));
+}
+
+/* Exact Jacobian (M2) of the helix step dx from sin(phi) = s1 with tan(lambda)
+ * = t, q/pT = c in a uniform field with curvature coefficient k = -kappa Bz
+ * (C = k c).  Also gives the step's dy and arc.  0 if |s2| >= 1. */
+static int helix_jacobian(double s1, double t, double c, double dx, double k, double J[5][5], double *dyo,
+                          double *arco)
+{
+    double cu = k * c;
     double s2 = s1 + cu * dx;
-    if (flags && near_lim(fabs(s2), g->snp_max, g->m_rel, g->m_snp)) *flags |= FL_P4;
-    if (!(fabs(s2) < g->snp_max)) return 0;
+    if (!(fabs(s2) < 1.0)) return 0;
     double f1 = sqrt(1.0 - s1 * s1);
     double f2 = sqrt(1.0 - s2 * s2);
-    double t = p[3];
     /* transverse displacement: integral of tan(phi) dx, written without 1/C */
     double dy = dx * (s1 + s2) / (f1 + f2);
     /* arc length from the chord */
@@ -211,8 +225,6 @@ static int propagate(double p[5], double C[5][5], double *x, double x2,
     double h = 0.5 * fabs(cu) * chord;
     double arc = (dx >= 0 ? chord : -chord) * (h > 0 ? asin(h) / h : 1.0);
     double delta = cu * arc;              /* turning angle */
-
-    double J[5][5];
     identity(J);
     J[0][2] = arc * sinc(delta) / (f1 * f2);
     J[0][4] = k * dx * dx / (f1 + f2) * (1.0 + s2 * (s1 + s2) / (f2 * (f1 + f2)));
@@ -223,10 +235,74 @@ static int propagate(double p[5], double C[5][5], double *x, double x2,
         J[1][4] = k * t * arc * arc * ((s2 / f2) * sh * sh * 0.5 + g_of(delta));
     }
     J[2][4] = k * dx;
+    *dyo = dy;
+    *arco = arc;
+    return 1;
+}
 
-    p[0] += dy;
-    p[1] += t * arc;
-    p[2] = s2;
+/* derivative of (y, z, sin phi) with respect to x along the track, and the
+ * field there */
+static int rk_deriv(const ocfg *g, double x, const double v[3], double t, double c, double d[3], double *bz)
+{
+    if (!(fabs(v[2]) < 1.0)) return 0;
+    double f = sqrt(1.0 - v[2] * v[2]);
+    *bz = field_at(g, x, v[0], v[1]);
+    d[0] = v[2] / f;
+    d[1] = t / f;
+    d[2] = -KAPPA * *bz * c;
+    return 1;
+}
+
+/* Helix step in the sector frame from *x to x2 with its Jacobian applied to
+ * C (if given).  Uniform field: the closed form (M1, M2).  Field map: the
+ * "maximal precision" step of Sect. 3 as a classical 4th-order Runge-Kutta
+ * integration of y' = tan(phi), z' = tan(lambda)/cos(phi), sin(phi)' =
+ * -kappa Bz(r, z) q/pT over equal x steps of at most field_step; the
+ * covariance is transported with the exact helix Jacobian over the whole
+ * step in the field the integration saw (the mean over the steps of the
+ * Runge-Kutta weighted field samples, (B1 + 2 B2 + 2 B3 + B4) / 6).
+ * Returns 0 (state untouched) if |sin phi| reaches snp_max. */
+static int propagate(double p[5], double C[5][5], double *x, double x2,
+                     const ocfg *g, unsigned *flags, double Jout[5][5])
+{
+    double dx = x2 - *x;
+    double k = -KAPPA * g->bz;            /* d curvature / d (q/pT) */
+    double J[5][5], dy, arc;
+    if (!field_map(g)) {
+        double s2 = p[2] + k * p[4] * dx;
+        if (flags && near_lim(fabs(s2), g->snp_max, g->m_rel, g->m_snp)) *flags |= FL_P4;
+        if (!(fabs(s2) < g->snp_max)) return 0;
+        if (!helix_jacobian(p[2], p[3], p[4], dx, k, J, &dy, &arc)) return 0;
+        p[0] += dy;
+        p[1] += p[3] * arc;
+        p[2] = s2;
+        *x = x2;
+        if (C) transport(J, C);
+        if (Jout) memcpy(Jout, J, sizeof(J));
+        return 1;
+    }
+    const int ns = (int)ceil(fabs(dx) / g->field_step);
+    const double h = ns > 0 ? dx / ns : 0.0, x1 = *x, t = p[3], c = p[4], s1 = p[2];
+    double bsum = 0.0, q[3] = {p[0], p[1], p[2]};
+    for (int i = 0; i < ns; i++) {
+        const double xa = x1 + i * h, xb = (i == ns - 1) ? x2 : x1 + (i + 1) * h;
+        const double hs = xb - xa;
+        double v[3] = {q[0], q[1], q[2]}, k1[3], k2[3], k3[3], k4[3], w[3], b1, b2, b3, b4;
+        if (!rk_deriv(g, xa, v, t, c, k1, &b1)) return 0;
+        for (int j = 0; j < 3; j++) w[j] = v[j] + 0.5 * hs * k1[j];
+        if (!rk_deriv(g, xa + 0.5 * hs, w, t, c, k2, &b2)) return 0;
+        for (int j = 0; j < 3; j++) w[j] = v[j] + 0.5 * hs * k2[j];
+        if (!rk_deriv(g, xa + 0.5 * hs, w, t, c, k3, &b3)) return 0;
+        for (int j = 0; j < 3; j++) w[j] = v[j] + hs * k3[j];
+        if (!rk_deriv(g, xb, w, t, c, k4, &b4)) return 0;
+        for (int j = 0; j < 3; j++) q[j] = v[j] + hs / 6.0 * (k1[j] + 2.0 * k2[j] + 2.0 * k3[j] + k4[j]);
+        bsum += (b1 + 2.0 * b2 + 2.0 * b3 + b4) / 6.0;
+        if (flags && near_lim(fabs(q[2]), g->snp_max, g->m_rel, g->m_snp)) *flags |= FL_P4;
+        if (!(fabs(q[2]) < g->snp_max)) return 0;
+    }
+    if (ns > 0) k = -KAPPA * bsum / ns;
+    if (!helix_jacobian(s1, t, c, dx, k, J, &dy, &arc)) return 0;
+    for (int j = 0; j < 3; j++) p[j] = q[j];
     *x = x2;
     if (C) transport(J, C);
     if (Jout) memcpy(Jout, J, sizeof(J));
@@ -245,7 +321,7 @@ static int rotate(double p[5], double C[5][5], double *x, double da,
     if (!(f1 > 0.0)) return 0;
     double x1 = *x * ca + p[0] * sa;
     double y1 = -*x * sa + p[0] * ca;
-    double cu = -KAPPA * g->bz * p[4];
+    double cu = -KAPPA * (field_map(g) ? field_at(g, *x, p[0], p[1]) : g->bz) * p[4];
     double J[5][5];
     identity(J);
     J[0][0] = f / f1;

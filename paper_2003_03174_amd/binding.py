@@ -66,6 +66,7 @@ class trd_config(C.Structure):
         ("vox_nx", C.c_int32), ("vox_ny", C.c_int32), ("vox_nz", C.c_int32), ("vox_min", C.c_int32),
         ("eloss_xrho", C.c_double), ("eloss_za", C.c_double), ("eloss_i", C.c_double),
         ("chamber_absent", C.c_uint8 * 540),
+        ("field_br", C.c_double), ("field_bz", C.c_double), ("field_step", C.c_double),
     ]
 
 
@@ -191,6 +192,9 @@ def make_config(params, precision="fp32", *, budget_bytes=0, block_size=0, searc
     if ab is not None:
         for d, v in enumerate(list(ab)[:540]):
             c.chamber_absent[d] = 1 if v else 0
+    c.field_br = float(params.get("field_br", 0.0))
+    c.field_bz = float(params.get("field_bz", 0.0))
+    c.field_step = float(params.get("field_step", 0.25))
     return c
 
 

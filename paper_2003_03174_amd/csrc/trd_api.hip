@@ -140,6 +140,8 @@ int check_config(const trd_config *c)
         return TRD_EINVAL;
     if ((int64_t)TRD_N_SECTORS * c->vox_nx * c->vox_ny * c->vox_nz > kMaxVoxels) return TRD_EINVAL;
     if (!(c->eloss_xrho >= 0 && c->eloss_xrho < 1e6)) return TRD_EINVAL;
+    if (!(fabs(c->field_br) < 1 && fabs(c->field_bz) < 1)) return TRD_EINVAL;
+    if ((c->field_br != 0 || c->field_bz != 0) && !(c->field_step > 0 && c->field_step <= 20)) return TRD_EINVAL;
     if (c->eloss_xrho > 0 && !(c->eloss_za > 0 && c->eloss_za < 2 && c->eloss_i > 0 && c->eloss_i < 1 &&
                                c->mass > 0 && isfinite(c->eloss_i)))
         return TRD_EINVAL;
@@ -185,6 +187,10 @@ void fill_devcfg(DevCfg<T> &g, const trd_config &c, const T *dx)
     for (int d = 0; d < TRD_N_DET; d++) dxm = fmax(dxm, fabs(c.dx_chamber[d]));
     g.dx_max = (T)dxm;
     g.dx = dx;
+    g.field_on = (c.field_br != 0 || c.field_bz != 0) ? 1 : 0;
+    g.fr = (T)(c.field_br / (370.0 * 370.0));
+    g.fz = (T)(c.field_bz / (360.0 * 360.0));
+    g.field_step = c.field_step;
     g.bin.y_min = -c.y_bin_w * c.n_yb / 2.0;
     g.bin.inv_w = 1.0 / c.y_bin_w;
     g.bin.dy_min = -c.dy_bin_w * c.n_db / 2.0;

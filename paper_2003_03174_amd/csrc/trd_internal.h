@@ -49,6 +49,10 @@ struct DevCfg {
     T tan_half_sector, cos_sector, sin_sector;  // tan(10 deg), cos/sin(20 deg)
     T dx_max;
     const T *dx;                               // [540] device
+    // field map: Bz = bz (1 + fr (x^2 + y^2) + fz z^2) in any sector frame
+    int field_on;
+    T fr, fz;
+    double field_step;                         // largest integration step (cm)
     BinCfg bin;
 };
 

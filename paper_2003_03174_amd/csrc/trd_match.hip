@@ -94,18 +94,15 @@ template <typename T> __device__ __forceinline__ T gfun(T d)
     return div_(T(sin(d)) - d, d * d);
 }
 
-// Helix step in the sector frame from T.x to x2, with the exact Jacobian
-// applied to the covariance.  False (state untouched) if |sin phi| would
-// reach snp_max.
+// The exact Jacobian of the helix step dx from sin(phi) = s1 with curvature
+// coefficient k (curvature k q/pT), applied to the covariance: C <- J C J^T.
+// The step's sin(phi) at the end, displacement and arc come with it.
 template <typename TS, typename TC>
-__device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS> &g)
+__device__ __forceinline__ void helix_transport(TC *C, TS s1, TS t, TS c, TS dx, TS k, TS &s2o, TS &dyo,
+                                                TS &arco)
 {
-    const TS dx = x2 - T.x;
-    const TS k = g.k_curv;
-    const TS cu = k * T.c;
-    const TS s1 = T.s;
+    const TS cu = k * c;
     const TS s2 = s1 + cu * dx;
-    if (!(fabs(s2) < g.snp_max)) return false;
     const TS f1 = sqrt(TS(1) - s1 * s1);
     const TS f2 = sqrt(TS(1) - s2 * s2);
     const TS ff = f1 + f2;
@@ -115,7 +112,6 @@ __device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS
     const TS aoh = asin_over(h);
     const TS arc = (dx >= TS(0) ? chord : -chord) * aoh;
     const TS delta = cu * arc;
-    const TS t = T.t;
 
     // Jacobian entries (identity elsewhere)
     const TC f12 = TC(f1) * TC(f2);
@@ -128,13 +124,10 @@ __device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS
     const TC f = TC(k) * TC(t) * sq(TC(arc)) *
                  ((TC(s2) / TC(f2)) * sh * sh * TC(0.5) + gfun(TC(delta)));  // dz/dc
     const TC gg = TC(k) * TC(dx);                                           // ds/dc
+    s2o = s2;
+    dyo = dy;
+    arco = arc;
 
-    T.y += dy;
-    T.z += t * arc;
-    T.s = s2;
-    T.x = x2;
-
-    TC *C = T.C;
     // D = J C (rows y, z, s change)
     const TC D00 = C[YY] + a * C[YS] + b * C[YC];
     const TC D01 = C[YZ] + a * C[ZS] + b * C[ZC];
@@ -161,6 +154,120 @@ __device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS
     C[SS] = D22 + gg * D24;
     C[ST] = D23;
     C[SC] = D24;
+}
+
+// Field of the map relative to its value on the axis at z = 0, at a point of
+// any sector frame (x^2 + y^2 is the squared radius).
+template <typename TS> __device__ __forceinline__ TS field_factor(TS x, TS y, TS z, const DevCfg<TS> &g)
+{
+    return TS(1) + g.fr * (x * x + y * y) + g.fz * z * z;
+}
+
+// d(y, z, sin phi)/dx and the field factor at (x, y, z); false if |sin phi| >= 1
+template <typename TS>
+__device__ __forceinline__ bool rk_deriv(TS x, TS y, TS z, TS s, TS t, TS kc, TS fr, TS fz, TS &dy, TS &dz,
+                                         TS &ds, TS &fb)
+{
+    if (!(fabs(s) < TS(1))) return false;
+    const TS rf = TS(1) / sqrt(TS(1) - s * s);
+    fb = TS(1) + fr * (x * x + y * y) + fz * z * z;
+    dy = s * rf;
+    dz = t * rf;
+    ds = kc * fb;
+    return true;
+}
+
+// y += v with the rounding error of the sum carried in e (compensated
+// summation: the many small steps of an integration do not lose the last
+// bits of the float state)
+template <typename TS> __device__ __forceinline__ void acc_add(TS &y, TS &e, TS v)
+{
+    const TS u = v - e;
+    const TS t = y + u;
+    e = (t - y) - u;
+    y = t;
+}
+
+template <typename TS> struct FieldStep {
+    TS y, z, s, k;
+    int ok;
+};
+
+// Step in a field map, state only: classical 4th-order Runge-Kutta
+// integration of y' = tan(phi), z' = tan(lambda)/cos(phi), sin(phi)' = k Bz/Bz0
+// q/pT over equal x steps of at most `step` (the step count in double, as the
+// double path computes it), with compensated sums of the steps.  Also the
+// curvature coefficient of the mean of the Runge-Kutta weighted field
+// samples, with which the caller transports the covariance.  ok = 0 if
+// |sin phi| reaches snp_max.  Kept out of line (scalars in and out) so that
+// the uniform-field path keeps its registers.
+template <typename TS>
+__device__ __noinline__ FieldStep<TS> field_step(TS x1, TS x2, TS y, TS z, TS s, TS t, TS c, TS kcurv, TS fr, TS fz,
+                                                 TS snp_max, double step)
+{
+    FieldStep<TS> r;
+    r.ok = 0;
+    r.y = y;
+    r.z = z;
+    r.s = s;
+    r.k = kcurv;
+    const TS dx = x2 - x1;
+    const int ns = (int)ceil(fabs((double)dx) / step);
+    const TS h = ns > 0 ? div_(dx, TS(ns)) : TS(0), kc = kcurv * c;
+    TS ey = TS(0), ez = TS(0), es = TS(0), fsum = TS(0);
+    for (int i = 0; i < ns; i++) {
+        const TS xa = x1 + TS(i) * h, xb = (i == ns - 1) ? x2 : x1 + TS(i + 1) * h;
+        const TS hs = xb - xa, hh = TS(0.5) * hs, xm = xa + hh;
+        TS a1, a2, a3, b1, b2, b3, c1, c2, c3, d1, d2, d3, f1, f2, f3, f4;
+        if (!rk_deriv(xa, y, z, s, t, kc, fr, fz, a1, a2, a3, f1)) return r;
+        if (!rk_deriv(xm, y + hh * a1, z + hh * a2, s + hh * a3, t, kc, fr, fz, b1, b2, b3, f2)) return r;
+        if (!rk_deriv(xm, y + hh * b1, z + hh * b2, s + hh * b3, t, kc, fr, fz, c1, c2, c3, f3)) return r;
+        if (!rk_deriv(xb, y + hs * c1, z + hs * c2, s + hs * c3, t, kc, fr, fz, d1, d2, d3, f4)) return r;
+        const TS w = hs * TS(1.0 / 6.0);
+        acc_add(y, ey, w * (a1 + TS(2) * b1 + TS(2) * c1 + d1));
+        acc_add(z, ez, w * (a2 + TS(2) * b2 + TS(2) * c2 + d2));
+        acc_add(s, es, w * (a3 + TS(2) * b3 + TS(2) * c3 + d3));
+        fsum += (f1 + TS(2) * f2 + TS(2) * f3 + f4) * TS(1.0 / 6.0);
+        if (!(fabs(s) < snp_max)) return r;
+    }
+    r.y = y;
+    r.z = z;
+    r.s = s;
+    r.k = ns > 0 ? kcurv * div_(fsum, TS(ns)) : kcurv;
+    r.ok = 1;
+    return r;
+}
+
+// Helix step in the sector frame from T.x to x2, with the exact Jacobian
+// applied to the covariance (in a field map: the state from field_step, the
+// covariance with the helix in its mean field).  False (state untouched) if
+// |sin phi| would reach snp_max.
+template <typename TS, typename TC>
+__device__ __forceinline__ bool propagate(Trk<TS, TC> &T, TS x2, const DevCfg<TS> &g)
+{
+    const TS dx = x2 - T.x;
+    TS k = g.k_curv;
+    FieldStep<TS> fs;
+    if (g.field_on) {
+        fs = field_step(T.x, x2, T.y, T.z, T.s, T.t, T.c, g.k_curv, g.fr, g.fz, g.snp_max, g.field_step);
+        if (!fs.ok) return false;
+        k = fs.k;
+        if (!(fabs(T.s + k * T.c * dx) < TS(1))) return false;
+    } else if (!(fabs(T.s + k * T.c * dx) < g.snp_max)) {
+        return false;
+    }
+    TS s2, dy, arc;
+    helix_transport(T.C, T.s, T.t, T.c, dx, k, s2, dy, arc);
+    if (g.field_on) {
+        T.y = fs.y;
+        T.z = fs.z;
+        T.s = fs.s;
+    } else {
+        T.y += dy;
+        T.z += T.t * arc;
+        T.s = s2;
+    }
+    T.x = x2;
     return true;
 }
 
@@ -177,7 +284,8 @@ __device__ __forceinline__ bool rotate(Trk<TS, TC> &T, bool up, const DevCfg<TS>
     const TS y1 = -T.x * sa + T.y * ca;
     const TC A = div_(TC(f), TC(f1));
     const TC B = div_(-TC(sa) * TC(T.t), TC(f1));
-    const TC Cc = -TC(g.k_curv) * TC(T.c) * TC(sa);
+    const TS kf = g.field_on ? g.k_curv * field_factor(T.x, T.y, T.z, g) : g.k_curv;
+    const TC Cc = -TC(kf) * TC(T.c) * TC(sa);
     const TC Dd = div_(TC(f1), TC(f));
     T.y = y1;
     T.s = s1;

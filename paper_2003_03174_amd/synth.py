@@ -71,6 +71,12 @@ def default_params(**over):
         eloss_za=0.5,
         eloss_i=1e-7,
         absent=np.zeros(N_DET, dtype=np.uint8),
+        # field inhomogeneity, off by default: Bz(r, z) = bz (1 + field_br
+        # (r / 370 cm)^2 + field_bz (z / 360 cm)^2), and the largest x step
+        # of the matcher's Runge-Kutta integration in such a field
+        field_br=0.0,
+        field_bz=0.0,
+        field_step=0.25,
     )
     for k, v in over.items():
         if k not in p:
@@ -120,6 +126,109 @@ def inclined_resolution(psi_deg=8.0):
 
     return dict(sigma_y=around(0.03, 0.5), sigma_dy=around(0.0015, 0.02),
                 tan_psi=math.tan(math.radians(psi_deg)))
+
+
+def field_map_overrides(br=-0.02, bz=-0.04):
+    """A field that falls off towards the ends of the solenoid and outwards:
+    2 % lower at the outer TRD radius, 4 % lower at the ends of the chambers
+    (the paper names field inhomogeneities in the precise extrapolation and
+    gives no map; this one is synthetic)."""
+    return dict(field_br=br, field_bz=bz)
+
+
+FIELD_RREF, FIELD_ZREF = 370.0, 360.0
+
+
+def field_at(P, X, Y, Z):
+    """Bz (T) of the field model at global (X, Y, Z)."""
+    r2 = X * X + Y * Y
+    return P["bz"] * (1.0 + P["field_br"] * r2 / FIELD_RREF ** 2 + P["field_bz"] * Z * Z / FIELD_ZREF ** 2)
+
+
+def _field_on(P):
+    return P.get("field_br", 0.0) != 0.0 or P.get("field_bz", 0.0) != 0.0
+
+
+def _rk_global(P, X, Y, Z, Phi, tg, c, ds):
+    """One classical Runge-Kutta step of length ds (transverse path, signed)
+    of the equation of motion in the global frame: X' = cos Phi, Y' = sin Phi,
+    Z' = tan(lambda), Phi' = -kappa Bz(X, Y, Z) q/pT (Bz only: pT and pz are
+    constant)."""
+    def f(Xa, Ya, Za, Pa):
+        return np.cos(Pa), np.sin(Pa), tg, -KAPPA * field_at(P, Xa, Ya, Za) * c
+    a = f(X, Y, Z, Phi)
+    b = f(X + 0.5 * ds * a[0], Y + 0.5 * ds * a[1], Z + 0.5 * ds * a[2], Phi + 0.5 * ds * a[3])
+    cc = f(X + 0.5 * ds * b[0], Y + 0.5 * ds * b[1], Z + 0.5 * ds * b[2], Phi + 0.5 * ds * b[3])
+    d = f(X + ds * cc[0], Y + ds * cc[1], Z + ds * cc[2], Phi + ds * cc[3])
+    k6 = ds / 6.0
+    return (X + k6 * (a[0] + 2 * b[0] + 2 * cc[0] + d[0]), Y + k6 * (a[1] + 2 * b[1] + 2 * cc[1] + d[1]),
+            Z + k6 * (a[2] + 2 * b[2] + 2 * cc[2] + d[2]), Phi + k6 * (a[3] + 2 * b[3] + 2 * cc[3] + d[3]))
+
+
+def _march(P, X, Y, Z, Phi, tg, c, level, dlevel, target, h, max_len):
+    """Steps of length h along the track (forward where target > level, else
+    backward) while the next one stays short of level == target, then Newton
+    on the last partial step.  level(X, Y) is the quantity that must reach
+    target, dlevel(X, Y, Phi) its derivative along the path.  Returns
+    (ok, X, Y, Z, Phi, s) with s the signed path length."""
+    sgn = np.where(level(X, Y) <= target, 1.0, -1.0)
+    s = np.zeros_like(X)
+    ok = np.ones(X.shape, dtype=bool)
+    active = ok.copy()
+    nmax = int(np.ceil(max_len / h)) + 2
+    for _ in range(nmax):
+        if not active.any():
+            break
+        Xn, Yn, Zn, Pn = _rk_global(P, X, Y, Z, Phi, tg, c, sgn * h)
+        passed = sgn * (level(Xn, Yn) - target) >= 0
+        step = active & ~passed
+        X, Y, Z, Phi = (np.where(step, Xn, X), np.where(step, Yn, Y), np.where(step, Zn, Z),
+                        np.where(step, Pn, Phi))
+        s = np.where(step, s + sgn * h, s)
+        active &= ~passed
+        # a track that turns away from the target never reaches it
+        away = active & (sgn * dlevel(X, Y, Phi) <= 0)
+        ok &= ~away
+        active &= ~away
+    ok &= ~active
+    # the partial step: Newton on its length
+    d = np.where(ok, (target - level(X, Y)) / np.where(ok, dlevel(X, Y, Phi), 1.0), 0.0)
+    for _ in range(6):
+        Xn, Yn, Zn, Pn = _rk_global(P, X, Y, Z, Phi, tg, c, d)
+        dl = dlevel(Xn, Yn, Pn)
+        ok &= dl * sgn > 0
+        d = d - np.where(ok, (level(Xn, Yn) - target) / np.where(ok, dl, 1.0), 0.0)
+    Xn, Yn, Zn, Pn = _rk_global(P, X, Y, Z, Phi, tg, c, d)
+    return ok, Xn, Yn, Zn, Pn, s + d
+
+
+def _cross_cylinder_field(P, phi0, tg, c, rho, dt, h=0.25):
+    """Crossing of a track from the origin with the cylinder r = rho in the
+    field model: (ok, X, Y, Z, Phi)."""
+    z0 = np.zeros(phi0.shape, dtype=dt)
+    ok, X, Y, Z, Phi, _ = _march(P, z0, z0.copy(), z0.copy(), phi0.astype(dt), tg, c,
+                                 lambda X, Y: np.hypot(X, Y),
+                                 lambda X, Y, Ph: np.where(np.hypot(X, Y) > 0,
+                                                           (X * np.cos(Ph) + Y * np.sin(Ph)) /
+                                                           np.maximum(np.hypot(X, Y), 1e-300), 1.0),
+                                 dt(rho), h, 4.0 * rho)
+    return ok, X, Y, Z, Phi
+
+
+def _cross_plane_field(P, X, Y, Z, Phi, tg, c, alpha, xl, dt, h=0.25):
+    """Crossing of the track through (X, Y, Z) with direction Phi with the
+    plane X cos(alpha) + Y sin(alpha) = xl of a sector, forwards or
+    backwards, in the field model.  Same outputs as _cross_plane, plus Z."""
+    ca, sa = np.cos(alpha), np.sin(alpha)
+    x0 = X * ca + Y * sa
+    ok, X1, Y1, Z1, Phi1, arc = _march(P, X, Y, Z, Phi, tg, c, lambda Xa, Ya: Xa * ca + Ya * sa,
+                                       lambda Xa, Ya, Pa: np.cos(Pa - alpha), xl, h,
+                                       4.0 * np.max(np.abs(np.asarray(xl - x0, dtype=np.float64)), initial=1.0) + 10.0)
+    y = -X1 * sa + Y1 * ca
+    phl = Phi1 - alpha
+    snp, csp = np.sin(phl), np.cos(phl)
+    ok &= csp > 0
+    return ok, y, snp, csp, X1, Y1, arc, Phi1, Z1
 
 
 def tilt_pm2deg():
@@ -256,12 +365,17 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
     tgl = np.sinh(eta)
     qpt = q / pt
 
-    # seed point: helix / cylinder r = rho_seed
+    # seed point: helix / cylinder r = rho_seed (in a field map: integrated)
+    fmap = _field_on(P)
     cu = (-KAPPA * bz * qpt).astype(dt)
-    ok0, phi_pos, phi_dir, arc0 = _cross_cylinder(phi0.astype(dt), cu, dt(rho_seed), dt)
-    X = dt(rho_seed) * np.cos(phi_pos)
-    Y = dt(rho_seed) * np.sin(phi_pos)
-    Z = tgl.astype(dt) * arc0
+    if fmap:
+        ok0, X, Y, Z, phi_dir = _cross_cylinder_field(P, phi0.astype(dt), tgl.astype(dt), qpt.astype(dt),
+                                                      rho_seed, dt)
+    else:
+        ok0, phi_pos, phi_dir, arc0 = _cross_cylinder(phi0.astype(dt), cu, dt(rho_seed), dt)
+        X = dt(rho_seed) * np.cos(phi_pos)
+        Y = dt(rho_seed) * np.sin(phi_pos)
+        Z = tgl.astype(dt) * arc0
     sec0 = _sector_of(X, Y)
     a0 = _alpha(sec0, dt)
     seed = np.zeros((5, n), dtype=np.float64)
@@ -306,18 +420,24 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
     truth = {k: np.full((N_LAYERS, n), np.nan) for k in ("x", "y", "z", "snp", "tgl", "qpt")}
     truth["sec"] = np.full((N_LAYERS, n), -1, dtype=np.int64)
     tk_rows = []   # per layer: (track ids, y, z, dy, det, row)
+
+    def cross(Xs, Ys, Zs, Phs, tgs, cs, alpha, xplane):
+        """(ok, y, snp, csp, X1, Y1, arc, Phi1) of the crossing with a sector plane"""
+        if fmap:
+            return _cross_plane_field(P, Xs, Ys, Zs, Phs, tgs, cs, alpha, xplane, dt)[:8]
+        return _cross_plane(Xs, Ys, Phs, -dt(KAPPA * bz) * cs, alpha, xplane, dt)
+
     for l in range(N_LAYERS):
         xl = dt(xl_arr[l])
-        cu = -dt(KAPPA * bz) * c
         a = _alpha(sec, dt)
-        ok, y, snp, csp, X1, Y1, arc, Phi1 = _cross_plane(X, Y, Phi, cu, a, xl, dt)
+        ok, y, snp, csp, X1, Y1, arc, Phi1 = cross(X, Y, Z, Phi, tg, c, a, xl)
         for _ in range(2):   # switch to the neighbouring sector that holds the point
             out = ok & (np.abs(y) > xl * dt(tan10))
             if not out.any():
                 break
             sec = np.where(out, np.mod(sec + np.where(y > 0, 1, -1), N_SECTORS), sec)
             a = _alpha(sec, dt)
-            ok2, y2, s2, c2, X2, Y2, arc2, Ph2 = _cross_plane(X, Y, Phi, cu, a, xl, dt)
+            ok2, y2, s2, c2, X2, Y2, arc2, Ph2 = cross(X, Y, Z, Phi, tg, c, a, xl)
             ok = np.where(out, ok2, ok)
             y, snp, csp = np.where(out, y2, y), np.where(out, s2, snp), np.where(out, c2, csp)
             X1, Y1 = np.where(out, X2, X1), np.where(out, Y2, Y1)
@@ -375,8 +495,7 @@ def generate_group(rng, params, n_tracks, *, pt_dist="exp", fake_ratio=0.2,
         stack = np.clip(zrow // P["n_rows"], 0, N_STACKS - 1)
         det = seca * (N_STACKS * N_LAYERS) + stack * N_LAYERS + l
         dxa = P["dx_chamber"][det].astype(dt)
-        cua = -dt(KAPPA * bz) * ca_
-        okt, yt, st, ct, _, _, arct, _ = _cross_plane(Xa, Ya, Pa, cua, aa, xl + dxa, dt)
+        okt, yt, st, ct, _, _, arct, _ = cross(Xa, Ya, Za, Pa, tga, ca_, aa, xl + dxa)
         zt = (Za + tga * arct).astype(np.float64)
         yt = yt.astype(np.float64)
         st = st.astype(np.float64)

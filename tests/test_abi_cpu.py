@@ -30,8 +30,9 @@ def test_config_struct_size_matches_header_layout():
     # 2 ints + 12 doubles + 2 doubles + 4 ints + 3 doubles + 540 + 3 + 3+3+1 + 4 doubles + u64 + 2 ints
     # + n_hyp (int, padded) + chi2_penalty + refit_cov[5] + refit_min (int, padded)
     # + tpc_x_in, tpc_x_out + 5 ints (padded) + 3 doubles (energy loss) + 540 bytes (padded to 544)
+    # + 3 doubles (field map)
     assert C.sizeof(B.trd_config) == (8 + 8 * 12 + 16 + 16 + 24 + 8 * 540 + 24 + 56 + 32 + 8 + 8 + 16 + 48 + 40
-                                      + 24 + 544)
+                                      + 24 + 544 + 24)
 
 
 def test_status_strings():

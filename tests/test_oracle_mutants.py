@@ -22,7 +22,12 @@ MUTANTS = {
     "transport_transposed": ("for (int k = 0; k < 5; k++) a += T[i][k] * J[j][k];",
                              "for (int k = 0; k < 5; k++) a += T[i][k] * J[k][j];"),
     "tilt_sign": ("double ry = yj - (ye + r->tau * (ze - zj));", "double ry = yj - (ye - r->tau * (ze - zj));"),
-    "curvature_sign": ("double cu = k * p[4];", "double cu = -k * p[4];"),
+    "curvature_sign": ("double k = -KAPPA * g->bz;            /* d curvature / d (q/pT) */",
+                       "double k = KAPPA * g->bz;"),
+    "field_z_term_dropped": ("+ g->field_bz * z * z / (FIELD_ZREF * FIELD_ZREF));", ");"),
+    "field_radius_local_x_only": ("const double r2 = x * x + y * y;", "const double r2 = x * x;"),
+    "rk_weights": ("hs / 6.0 * (k1[j] + 2.0 * k2[j] + 2.0 * k3[j] + k4[j])",
+                   "hs / 6.0 * (k1[j] + 2.0 * k2[j] + 2.0 * k2[j] + k4[j])"),
     "rotation_ds_dy_sign": ("J[2][0] = -cu * sa;", "J[2][0] = cu * sa;"),
     "dy_gate_slope_power": ("C[2][2] / (f3 * f3));", "C[2][2] / (f3));"),
     "chi2_cross_term": ("2.0 * r->Si[0][1] * ry * rz", "r->Si[0][1] * ry * rz"),
@@ -73,7 +78,7 @@ MUTANTS = {
 
 PINS = ["test_oracle_math.py", "test_oracle_search.py", "test_oracle_beam.py", "test_oracle_refit.py",
         "test_oracle_residuals.py", "test_oracle_realistic.py", "test_oracle_resolution.py",
-        "test_oracle_flags.py"]
+        "test_oracle_flags.py", "test_oracle_field.py"]
 
 
 def _run_mutant(name, tmp):
