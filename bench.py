@@ -487,7 +487,12 @@ def main():
         d = binding.device_inputs(synth.to_device_layout(w), args.precision)
         tuned = autotune.tune(P, d, ng, args.precision, use_cache=False)
         args.block_size, args.search_lanes = tuned["block_size"], tuned["search_lanes"]
-        log(f"autotuned: block {args.block_size}, lanes {args.search_lanes} ({tuned['ms']:.3f} ms)")
+        args.persistent = tuned["persistent"]
+        w = dict(w, params=dict(P, **tuned["bins"]))
+        P = w["params"]
+        n_cells = ng * 540 * P["n_rows"] * P["n_yb"] * P["n_db"]
+        log(f"autotuned: bins {tuned['bins']}, block {args.block_size}, lanes {args.search_lanes}, "
+            f"persistent {args.persistent} ({tuned['ms']:.3f} ms)")
         del d
     from paper_2003_03174_amd import binding
     r = run_gpu(w, args.precision, args.steps, args.warmup, args.block_size, args.search_lanes,
@@ -540,7 +545,8 @@ def main():
                   "tracks_per_s": n / (sum(r["refit_ms"]) / len(r["refit_ms"]) * 1e-3),
                   "what": "TRD-only refit of all matched tracks (one launch, after the timed steps)"},
         "fp64_fallback_tracks": r["n_fallback"],
-        "autotune": tuned["table"] if tuned else None,
+        "autotune": {"bins": tuned["bins"], "bin_table": tuned["bin_table"], "shapes": tuned["table"]}
+                    if tuned else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_match_beam" if args.n_hyp else "k_match", "alg_bytes_per_launch": ab,

@@ -7,6 +7,7 @@ from oracle import oracle as O
 from paper_2003_03174_amd import binding as B
 from paper_2003_03174_amd import synth
 from tests import parity_util as pu
+from tests.test_gpu_parity import run_gpu
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -93,13 +94,24 @@ def test_multiframe_batch_graph_full_size_sampled():
     assert np.array_equal(w["tkl_group"][idx[mk]], np.broadcast_to(w["group"], idx.shape)[mk])
 
 
-def test_autotune_picks_a_listed_shape(tmp_path):
+def test_autotune_picks_a_listed_shape_and_geometry(tmp_path):
+    """The tuner times the listed cell geometries, then the launch shapes
+    (and the persistent grid with one lane per track) with the best one; its
+    choice gives results bit-identical to the workload's own geometry (the
+    search does not depend on the bins); the cache returns the same record."""
     from paper_2003_03174_amd import autotune
     w = synth.generate("c2_frame_20k")
     d = B.device_inputs(synth.to_device_layout(w), "fp32")
+    geos = [dict(y_bin_w=4.0, n_yb=32, dy_bin_w=0.0625, n_db=1), dict(y_bin_w=16.0, n_yb=8, dy_bin_w=0.0625, n_db=1)]
     r = autotune.tune(w["params"], d, 1, "fp32", shapes=((256, 1), (256, 8), (128, 4)), reps=2,
-                      cache_path=str(tmp_path / "c.json"))
+                      cache_path=str(tmp_path / "c.json"), geometries=geos)
     assert (r["block_size"], r["search_lanes"]) in {(256, 1), (256, 8), (128, 4)}
-    assert len(r["table"]) == 3 and all(t[2] > 0 for t in r["table"])
+    assert len(r["table"]) == 4 and all(t[3] > 0 for t in r["table"])
+    assert len(r["bin_table"]) == 3 and r["bins"] in geos + [dict(y_bin_w=8.0, n_yb=16, dy_bin_w=0.0625, n_db=1)]
     r2 = autotune.tune(w["params"], d, 1, "fp32", cache_path=str(tmp_path / "c.json"))
     assert r2["table"] == [list(t) for t in r["table"]] or r2["table"] == r["table"]
+    base = run_gpu(w, "fp32")
+    for gq in geos:
+        o = run_gpu(w, "fp32", params=dict(w["params"], **gq))
+        for k in ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status"):
+            assert np.array_equal(o[k], base[k], equal_nan=True), (gq, k)
