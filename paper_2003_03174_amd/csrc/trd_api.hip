@@ -232,9 +232,13 @@ int64_t hist_len(int64_t n) { return radix_blocks(n > 0 ? n : 1) * 256; }
 int64_t tkl_bytes(int64_t n)
 {
     const int64_t m = n > 0 ? n : 1;
-    return m * (4 + 4 + 16 + 16) + 8 * hist_len(n) + 4 * scan_block_sums_len(hist_len(n));
+    return m * (4 + 4 + 16 + 16) + 8 * tkl_hist_len(n) + 4 * scan_block_sums_len(tkl_hist_len(n));
 }
-int64_t cell_bytes(int64_t nc) { return 4 * (nc + 1); }
+// chamber slots of nc cells (cells per slot: n_rows * n_db * n_yb)
+int64_t n_slots_of(const trd_config &c, int64_t nc) { return nc / ((int64_t)c.n_rows * c.n_db * c.n_yb); }
+// offsets [nc + 1], then the first position of each slot [slots + 2]
+int64_t cell_entries(const trd_config &c, int64_t nc) { return nc + 1 + n_slots_of(c, nc) + 2; }
+int64_t cell_bytes(const trd_config &c, int64_t nc) { return 4 * cell_entries(c, nc); }
 // tracks are matched in a spatial order (rows of state in, rows of results
 // out) unless the caller keeps its own order or the launch shape has no use
 // for it (several lanes per road)
@@ -284,7 +288,7 @@ int ensure_tkl(trd_ctx *ctx, int64_t n)
     ctx->cap_tkl = 0;
     int64_t acc = 0;
     int rc;
-    const int64_t hl = hist_len(cap);
+    const int64_t hl = tkl_hist_len(cap);
     if ((rc = dev_alloc(ctx, &ctx->d_keys_a, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_keys_b, cap, &acc)) ||
         (rc = dev_alloc(ctx, &ctx->d_sorted, cap, &acc)) || (rc = dev_alloc(ctx, &ctx->d_tmp, cap, &acc)) ||
         (rc = dev_alloc(ctx, &ctx->d_hist, hl, &acc)) || (rc = dev_alloc(ctx, &ctx->d_hist_off, hl, &acc)) ||
@@ -300,15 +304,15 @@ int ensure_tkl(trd_ctx *ctx, int64_t n)
 int ensure_cells(trd_ctx *ctx, int64_t nc)
 {
     if (nc <= ctx->cap_cells && ctx->d_offsets) return TRD_OK;
-    const int64_t old = ctx->d_offsets ? cell_bytes(ctx->cap_cells) : 0;
-    if (over_budget(ctx, cell_bytes(nc) - old)) return TRD_EBUDGET;
+    const int64_t old = ctx->d_offsets ? cell_bytes(ctx->cfg, ctx->cap_cells) : 0;
+    if (over_budget(ctx, cell_bytes(ctx->cfg, nc) - old)) return TRD_EBUDGET;
     dev_free(&ctx->d_offsets);
     ctx->bytes -= old;
     ctx->cap_cells = 0;
     int64_t acc = 0;
-    const int rc = dev_alloc(ctx, &ctx->d_offsets, nc + 1, &acc);
+    const int rc = dev_alloc(ctx, &ctx->d_offsets, cell_entries(ctx->cfg, nc), &acc);
     if (rc) return rc;
-    ctx->bytes += cell_bytes(nc);
+    ctx->bytes += cell_bytes(ctx->cfg, nc);
     ctx->cap_cells = nc;
     return TRD_OK;
 }
@@ -498,6 +502,7 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
     buf.hist_off = ctx->d_hist_off;
     buf.tiles_tkl = ctx->d_tiles_tkl;
     buf.offsets = ctx->d_offsets;
+    buf.bstart = ctx->d_offsets + ctx->cap_cells + 1;
     launch_bin(t->y, t->z, t->dy, t->det_row, t->group, n, b, buf, s);
     if ((rc = launch_status())) return rc;
     ctx->loaded = true;

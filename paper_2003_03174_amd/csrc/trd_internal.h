@@ -58,19 +58,22 @@ struct DevCfg {
 
 // Device buffers of the binning.
 struct BinBuffers {
-    uint32_t *keys_a, *keys_b;  // [cap] cell keys (radix ping-pong)
-    float4 *sorted, *recs_tmp;  // [cap] records (radix ping-pong; result in `sorted`)
-    uint32_t *hist, *hist_off;  // [radix_blocks(cap) * 256] digit histograms
-    uint32_t *tiles_tkl;        // [scan_block_sums_len(radix_blocks(cap) * 256)]
+    uint32_t *keys_a, *keys_b;  // [cap] cell keys (partition ping-pong)
+    float4 *sorted, *recs_tmp;  // [cap] records (partition ping-pong; result in `sorted`)
+    uint32_t *hist, *hist_off;  // [tkl_hist_len(cap)] digit histograms
+    uint32_t *tiles_tkl;        // [scan_block_sums_len(tkl_hist_len(cap))]
     uint32_t *offsets;          // [n_cells + 1]
+    uint32_t *bstart;           // [n_groups * kDet + 2] first position of each bucket
 };
 
 // launchers (stream-ordered, no synchronisation)
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 int64_t scan_block_sums_len(int64_t n);
 int64_t radix_blocks(int64_t n);
+int64_t tkl_hist_len(int64_t n);  // histogram entries of the tracklet partition of n
 // sorts the tracklets into cells: buf.sorted in (key, input index) order,
-// buf.offsets[c] = first position of cell c, offsets[n_cells] = valid count
+// buf.offsets[c] = first position of cell c, offsets[n_cells] = valid count;
+// the tracklets without a cell follow in input order
 void launch_bin(const float *y, const float *z, const float *dy, const uint32_t *det_row,
                 const int32_t *grp, int64_t n, const BinCfg &b, BinBuffers &buf, hipStream_t s);
 

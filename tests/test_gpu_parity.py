@@ -102,6 +102,18 @@ def test_deflection_bins(prec, tilt):
     assert rep.ok, rep.summary()
 
 
+def test_cells_per_chamber_above_one_chunk():
+    """More cells per chamber (4 cm y bins x 1/8 cm dy bins x 16 rows = 32768)
+    than the cell sort orders in one LDS chunk: binning bit-exact, parity."""
+    params = dict(y_bin_w=4.0, n_yb=32, dy_bin_w=0.125, n_db=64)
+    w = workload(None, n_tracks=3000, seed=31, fake_ratio=0.5, ineff_frac=0.1, params=params)
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_cov64", "fp32"])
 def test_frame_20k(prec):
     w = workload("c2_frame_20k")
@@ -123,6 +135,20 @@ def test_multi_frame_groups():
     assert rep.ok, rep.summary()
     m = res["idx"] >= 0
     assert np.array_equal(w["tkl_group"][res["idx"][m]], np.broadcast_to(w["group"], m.shape)[m])
+
+
+def test_multi_frame_groups_with_deflection_bins():
+    """Five groups of 540 chambers with 36 deflection bins: chambers too large
+    to be sorted together, so the partition by chamber takes two passes
+    (an 11-bit digit, then an 8-bit one).  Binning bit-exact, parity."""
+    w = synth.generate_frames(4, 5, [900, 1, 2000, 400, 1500], [0.5, 0.2, 0.7, 0.4, 0.6],
+                              params_over=dict(y_bin_w=8.0, n_yb=16, dy_bin_w=0.25, n_db=36),
+                              ineff_frac=0.1)
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
 
 
 def test_distortion_batch_full_size_sampled():
