@@ -103,10 +103,22 @@ def test_deflection_bins(prec, tilt):
 
 
 def test_cells_per_chamber_above_one_chunk():
-    """More cells per chamber (4 cm y bins x 1/8 cm dy bins x 16 rows = 32768)
-    than the cell sort orders in one LDS chunk: binning bit-exact, parity."""
+    """More cells per chamber (4 cm y bins x 1/8 cm dy bins x 18 rows) than
+    the cell sort orders in one LDS chunk: binning bit-exact, parity."""
     params = dict(y_bin_w=4.0, n_yb=32, dy_bin_w=0.125, n_db=64)
     w = workload(None, n_tracks=3000, seed=31, fake_ratio=0.5, ineff_frac=0.1, params=params)
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
+
+
+def test_cells_per_bucket_above_one_chunk():
+    """A chamber of 1 cm y bins x 1/16 cm dy bins x 18 rows (294912 cells):
+    the cell sort goes over 18 LDS chunks: binning bit-exact, parity."""
+    params = dict(y_bin_w=1.0, n_yb=128, dy_bin_w=0.0625, n_db=128)
+    w = workload(None, n_tracks=1500, seed=37, fake_ratio=0.5, ineff_frac=0.1, params=params)
     res = run_gpu(w, "fp32")
     check_binning(w, res)
     ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
