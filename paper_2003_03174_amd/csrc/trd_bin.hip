@@ -190,9 +190,10 @@ struct SlotPassSrc {
 };
 
 // digit histogram of one tile, stored digit-major: hist[d * n_blocks + block]
+// (only the first nd digits are stored: the ones that occur)
 template <typename Src, int kBits>
 __global__ void __launch_bounds__(kBlock)
-    k_radix_hist(Src src, int64_t n, int shift, uint32_t *__restrict__ hist, uint32_t *__restrict__ key_out)
+    k_radix_hist(Src src, int64_t n, int shift, int nd, uint32_t *__restrict__ hist, uint32_t *__restrict__ key_out)
 {
     constexpr int kNb = 1 << kBits;
     __shared__ uint32_t h[kNb];
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kNb; d += kBlock) hist[(int64_t)d * gridDim.x + tile] = h[d];
+    for (int d = threadIdx.x; d < nd; d += kBlock) hist[(int64_t)d * gridDim.x + tile] = h[d];
 }
 
 // Stable scatter of one tile: elements are taken in input order (sub-tile,
@@ -317,7 +318,7 @@ __global__ void __launch_bounds__(kBlock)
 // footprint keeps many workgroups resident).
 template <typename Src, int kBits>
 __global__ void __launch_bounds__(kBlock)
-    k_wide_scatter(Src src, int64_t n, int shift, const uint32_t *__restrict__ hist_off,
+    k_wide_scatter(Src src, int64_t n, int shift, int nd, const uint32_t *__restrict__ hist_off,
                    uint32_t *__restrict__ keys_out, typename Src::Rec *__restrict__ recs_out)
 {
     using Rec = typename Src::Rec;
@@ -327,7 +328,7 @@ __global__ void __launch_bounds__(kBlock)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const unsigned tile = xcd_tile();
     for (int d = tid; d < kNb; d += kBlock) {
-        glob[d] = hist_off[(int64_t)d * gridDim.x + tile];
+        glob[d] = d < nd ? hist_off[(int64_t)d * gridDim.x + tile] : 0u;
 #pragma unroll
         for (int w = 0; w < kWaves; w++) wc[w][d] = 0;
     }
@@ -459,8 +460,8 @@ __device__ __forceinline__ int class_entry(int u, int w, int c) { return (u * kO
 
 __global__ void __launch_bounds__(kOrderBlock)
     k_cell_order(const uint32_t *__restrict__ keys, const float4 *__restrict__ recs,
-                 const uint32_t *__restrict__ bounds, int64_t n, uint32_t cells, uint32_t chunk,
-                 uint32_t n_slots, float4 *__restrict__ sorted, uint32_t *__restrict__ offsets)
+                 const uint32_t *__restrict__ bounds, int64_t bstride, int64_t n, uint32_t cells,
+                 uint32_t chunk, uint32_t n_slots, float4 *__restrict__ sorted, uint32_t *__restrict__ offsets)
 {
     extern __shared__ uint32_t lds[];
     uint32_t *cur = lds;                                          // [chunk] cell cursors
@@ -469,7 +470,9 @@ __global__ void __launch_bounds__(kOrderBlock)
     __shared__ uint16_t ccnt[kClassEntries];  // per (sub-tile, wavefront, class): count, then offset
     __shared__ uint32_t cls_end[kOrderWaves];
     const uint32_t sl = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    uint32_t end = bounds[sl + 1], start = bounds[sl];
+    // bucket b starts at bounds[b * bstride]; the last one ends at n
+    uint32_t end = sl < n_slots ? bounds[(int64_t)(sl + 1) * bstride] : (uint32_t)n;
+    uint32_t start = bounds[(int64_t)sl * bstride];
     end = end > (uint64_t)n ? (uint32_t)n : end;
     start = start > end ? end : start;
     if (sl == n_slots) {
@@ -596,14 +599,15 @@ __global__ void __launch_bounds__(kOrderBlock)
     }
 }
 
-// load the kScanItems values owned by this thread (pad past the end)
+// load the N values owned by this thread (pad past the end)
+template <int N>
 __device__ __forceinline__ void load_items(const uint32_t *in, int64_t n, int64_t base, uint32_t pad,
-                                           uint32_t (&v)[kScanItems])
+                                           uint32_t (&v)[N])
 {
-    if (base + kScanItems <= n) {
+    if (base + N <= n) {
         const uint4 *q = reinterpret_cast<const uint4 *>(in + base);
 #pragma unroll
-        for (int j = 0; j < kScanItems / 4; j++) {
+        for (int j = 0; j < N / 4; j++) {
             const uint4 u = q[j];
             v[4 * j] = u.x;
             v[4 * j + 1] = u.y;
@@ -612,22 +616,22 @@ __device__ __forceinline__ void load_items(const uint32_t *in, int64_t n, int64_
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < kScanItems; j++) v[j] = (base + j < n) ? in[base + j] : pad;
+        for (int j = 0; j < N; j++) v[j] = (base + j < n) ? in[base + j] : pad;
     }
 }
 
-// store the kScanItems values owned by this thread (nothing past the end)
-__device__ __forceinline__ void store_items(uint32_t *out, int64_t n, int64_t base,
-                                            const uint32_t (&v)[kScanItems])
+// store the N values owned by this thread (nothing past the end)
+template <int N>
+__device__ __forceinline__ void store_items(uint32_t *out, int64_t n, int64_t base, const uint32_t (&v)[N])
 {
-    if (base + kScanItems <= n) {
+    if (base + N <= n) {
         uint4 *q = reinterpret_cast<uint4 *>(out + base);
 #pragma unroll
-        for (int j = 0; j < kScanItems / 4; j++)
+        for (int j = 0; j < N / 4; j++)
             q[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
     } else {
 #pragma unroll
-        for (int j = 0; j < kScanItems; j++)
+        for (int j = 0; j < N; j++)
             if (base + j < n) out[base + j] = v[j];
     }
 }
@@ -710,7 +714,7 @@ static void radix_pass(const Src &src, int64_t n, int shift, uint32_t *hist, uin
 {
     const int64_t nblk = radix_blocks(n);
     hipLaunchKernelGGL((k_radix_hist<Src, kRadixBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift,
-                       hist, (uint32_t *)nullptr);
+                       kBins, hist, (uint32_t *)nullptr);
     launch_excl_scan(hist, nblk * kBins, tiles, hist_off, s);
     hipLaunchKernelGGL(k_radix_scatter<Src>, dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, shift, hist,
                        hist_off, keys_out, recs_out, rank_out);
@@ -720,16 +724,16 @@ static void radix_pass(const Src &src, int64_t n, int shift, uint32_t *hist, uin
 // the histogram pass computes the keys once and leaves them in key_cache for
 // the scatter.
 template <int kBits>
-static void wide_pass_tkl(TklSrc src, int64_t n, uint32_t *key_cache, uint32_t *hist, uint32_t *hist_off,
+static void wide_pass_tkl(TklSrc src, int64_t n, int nd, uint32_t *key_cache, uint32_t *hist, uint32_t *hist_off,
                           uint32_t *tiles, uint32_t *keys_out, float4 *recs_out, hipStream_t s)
 {
     const int64_t nblk = radix_blocks(n);
     src.cached = nullptr;
-    hipLaunchKernelGGL((k_radix_hist<TklSrc, kBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, hist,
-                       key_cache);
-    launch_excl_scan(hist, nblk * (1 << kBits), tiles, hist_off, s);
+    hipLaunchKernelGGL((k_radix_hist<TklSrc, kBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, nd,
+                       hist, key_cache);
+    launch_excl_scan(hist, nblk * nd, tiles, hist_off, s);
     src.cached = key_cache;
-    hipLaunchKernelGGL((k_wide_scatter<TklSrc, kBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0,
+    hipLaunchKernelGGL((k_wide_scatter<TklSrc, kBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, nd,
                        hist_off, keys_out, recs_out);
 }
 
@@ -770,14 +774,16 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
     uint32_t *kdst[2] = {buf.keys_a, buf.keys_b};
     float4 *rdst[2] = {buf.recs_tmp, buf.sorted};
     int out = (passes - 1) & 1;
+    // digits of the first pass that occur: every bucket of a one-pass partition
+    const int nd = passes == 1 ? (int)n_slots + 1 : 1 << wide;
     if (n > 0) {
         // the other key buffer is free during the first pass
         const TklSrc src{y, z, dy, det_row, grp, b, slot, nullptr};
         if (wide == 10)
-            wide_pass_tkl<10>(src, n, kdst[out ^ 1], buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out], rdst[out],
-                              s);
+            wide_pass_tkl<10>(src, n, nd, kdst[out ^ 1], buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
+                              rdst[out], s);
         else
-            wide_pass_tkl<kWideBits>(src, n, kdst[out ^ 1], buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
+            wide_pass_tkl<kWideBits>(src, n, nd, kdst[out ^ 1], buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
                                      rdst[out], s);
         for (int p = 1; p < passes; p++) {
             const SlotPassSrc ps{kdst[out], rdst[out], slot};
@@ -786,16 +792,25 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
                        rdst[out], s);
         }
     }
-    // out == 0 here: keys_a and recs_tmp hold the tracklets in bucket order
-    hipLaunchKernelGGL(k_slot_bounds, dim3(grid_for(n + 1, kBlock)), dim3(kBlock), 0, s, buf.keys_a, n, slot,
-                       n_slots + 2, buf.bstart);
+    // out == 0 here: keys_a and recs_tmp hold the tracklets in bucket order.
+    // After a one-pass partition, bucket b starts where its digit starts for
+    // the first tile (hist_off[b * tiles]); otherwise the starts are found
+    // from the partitioned keys.
+    const uint32_t *bnd = buf.hist_off;
+    int64_t bstride = radix_blocks(n);
+    if (n == 0 || passes > 1) {
+        hipLaunchKernelGGL(k_slot_bounds, dim3(grid_for(n + 1, kBlock)), dim3(kBlock), 0, s, buf.keys_a, n, slot,
+                           n_slots + 2, buf.bstart);
+        bnd = buf.bstart;
+        bstride = 1;
+    }
     const uint32_t chunk = cells < kCellChunk ? cells : kCellChunk;
     const size_t lds = (chunk + kSeg) * sizeof(uint32_t) + kSeg * sizeof(uint16_t);
     if (lds > 65536)  // up to 88 KB for a full chunk
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cell_order),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_cell_order, dim3(n_slots + 1), dim3(kOrderBlock), lds, s, buf.keys_a, buf.recs_tmp,
-                       buf.bstart, n, cells, chunk, n_slots, buf.sorted, buf.offsets);
+    hipLaunchKernelGGL(k_cell_order, dim3(n_slots + 1), dim3(kOrderBlock), lds, s, buf.keys_a, buf.recs_tmp, bnd,
+                       bstride, n, cells, chunk, n_slots, buf.sorted, buf.offsets);
 }
 
 template <typename TS>

@@ -1061,10 +1061,11 @@ __device__ __forceinline__ unsigned xcd_block()
 // the extra waves in flight are worth a few spilled registers; the
 // several-hypotheses kernel takes four too: 2.06 -> 1.40 ms on the 450k
 // batch with four hypotheses).  Float state with a double covariance: three
-// (0.56 -> 0.49 ms).  Double state: the compiler's choice (two; three or
-// four spill and lose 10-20 %).
+// (0.56 -> 0.49 ms).  Double state: two (256 registers and a few spilled;
+// left to itself the compiler takes 256 plus accumulation registers for one
+// wave, 1.05 ms instead of 0.79 ms; three or four spill and lose 10-20 %).
 template <typename TS, typename TC>
-constexpr int kMinWaves = sizeof(TC) == 4 ? 4 : (sizeof(TS) == 4 ? 3 : 1);
+constexpr int kMinWaves = sizeof(TC) == 4 ? 4 : (sizeof(TS) == 4 ? 3 : 2);
 
 // One lane per track (the plain kernel; double precision runs here).
 template <typename TS, typename TC, bool kFloatCov>
