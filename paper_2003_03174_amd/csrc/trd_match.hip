@@ -686,7 +686,8 @@ __device__ __forceinline__ TS cand_chi2(const Road<TS> &R, TS ye, TS ze, const f
     const TS ddy = TS(r.y) - R.dytrk;
     const TS zj = TS(r.z);
     const TS rz = zj - ze;
-    const TS ry = TS(r.x) - (ye + R.tau * (ze - zj));
+    // y of the track at the tracklet's z along the tilted pad: ye + tau (ze - zj)
+    const TS ry = TS(r.x) - (ye - R.tau * rz);
     const TS chi2 = R.si00 * ry * ry + TS(2) * R.si01 * ry * rz + R.si11 * rz * rz;
     pass = fabs(ddy) <= R.gdy && fabs(rz) <= R.Rz && fabs(ry) <= R.Ry && chi2 <= chi2_max;
     return chi2;
@@ -794,29 +795,35 @@ __device__ __forceinline__ void scan_road_lane(const Road<TS> &R, const DevCfg<T
     }
 }
 
-// Gate one record of stack st and offer it to the accumulator.
-template <typename TS, typename A>
+// Gate one record of stack st (chamber shifted by dxd in x when kShift) and
+// offer it to the accumulator unless `in` is false.
+template <bool kShift, typename TS, typename A>
 __device__ __forceinline__ void gate_record(const Road<TS> &R, const DevCfg<TS> &g, const float4 &rec,
-                                            int st, TS dxd, A &acc)
+                                            int st, TS dxd, bool in, A &acc)
 {
-    const TS ye = R.y + dxd * R.tphi, ze = R.z + dxd * R.tz;
+    TS ye = R.y, ze = R.z;
+    if (kShift) {
+        ye = R.y + dxd * R.tphi;
+        ze = R.z + dxd * R.tz;
+    }
     bool pass;
     const TS c = cand_chi2(R, ye, ze, rec, g.chi2_max, pass);
-    acc.offer(c, __float_as_int(rec.w), rec.x, rec.z, st, pass);
+    acc.offer(c, __float_as_int(rec.w), rec.x, rec.z, st, pass & in);
 }
 
 // One lane walks a whole road with its records flattened: the bounds of up
 // to kBatch ranges come in one memory round trip, then their records are
 // taken kU at a time across range boundaries, so a round trip fetches kU
-// records however the road's candidates fall into cells.
-template <typename TS, typename A>
-__device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
-                                               A &B)
+// records however the road's candidates fall into cells.  kShift: chambers
+// are shifted in x (misalignment), so each record's stack moves the
+// track's point.
+template <bool kShift, typename TS, typename A>
+__device__ __forceinline__ void scan_road_flat_k(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                                 A &B)
 {
     constexpr int kBatch = 4, kU = 4;
     const int nr = g.bin.n_rows;
     const RangeGrid q = range_grid(R, nr);
-    const bool shifted = g.dx_max != TS(0);
     // Cell index of the first pad row of range (is, id, iy), kept as a running
     // sum: one y bin further adds sy, the next dy bin (y back to the first)
     // adds sy + wy, the next stack (dy and y back to the first) adds ws on top
@@ -861,31 +868,39 @@ __device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<T
         for (uint32_t f0 = 0; f0 < tot; f0 += kU) {
             float4 rec[kU];
             int su[kU];
+            bool in[kU];
             TS dxd[kU];
 #pragma unroll
             for (int u = 0; u < kU; u++) {
-                const uint32_t f = f0 + (uint32_t)u;
+                // past the end: the batch's last record again, offered as failing
+                in[u] = f0 + (uint32_t)u < tot;
+                const uint32_t f = in[u] ? f0 + (uint32_t)u : tot - 1u;
                 // the range holding flat position f: the last one starting at or before it
                 uint32_t k = a[0] + f;
                 su[u] = st[0];
 #pragma unroll
                 for (int q = 1; q < kBatch; q++) {
-                    const bool in = f >= pre[q];
-                    k = in ? a[q] + (f - pre[q]) : k;
-                    su[u] = in ? st[q] : su[u];
+                    const bool past = f >= pre[q];
+                    k = past ? a[q] + (f - pre[q]) : k;
+                    su[u] = past ? st[q] : su[u];
                 }
-                dxd[u] = TS(0);
-                // past the end: a record whose NaN position fails every gate
-                rec[u] = make_float4(__builtin_nanf(""), 0.f, 0.f, __int_as_float(0x7fffffff));
-                if (f < tot) {
-                    rec[u] = io.sorted[k];
-                    if (shifted) dxd[u] = g.dx[R.sdet0 + su[u] * kLayers];
-                }
+                rec[u] = io.sorted[k];
+                dxd[u] = kShift ? g.dx[R.sdet0 + su[u] * kLayers] : TS(0);
             }
 #pragma unroll
-            for (int u = 0; u < kU; u++) gate_record(R, g, rec[u], su[u], dxd[u], B);
+            for (int u = 0; u < kU; u++) gate_record<kShift>(R, g, rec[u], su[u], dxd[u], in[u], B);
         }
     }
+}
+
+template <typename TS, typename A>
+__device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                               A &B)
+{
+    if (g.dx_max != TS(0))
+        scan_road_flat_k<true>(R, g, io, B);
+    else
+        scan_road_flat_k<false>(R, g, io, B);
 }
 
 // G lanes share a road: lane `sub` takes every G-th range.
