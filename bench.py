@@ -79,7 +79,7 @@ def profiled_valu():
     return {"issue_frac": a, "lane_frac": b, "source": os.path.relpath(PROFILE, ROOT)}
 
 
-def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None, flags=0):
+def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d=None, flags=0, fused=True):
     import torch
     from paper_2003_03174_amd import binding as B
     from paper_2003_03174_amd import synth
@@ -94,9 +94,16 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
     out = m.alloc_results(n, chi2_layer=False)
     stream = torch.cuda.current_stream()
 
+    def load_and_match():
+        m.load_and_match(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"], d["p"], d["cov"],
+                         d["x"], d["sector"], tgroup=d["group"], out=out)
+
     def body():
-        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
-        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+        if fused:
+            load_and_match()
+        else:
+            m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+            m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
 
     g = None
     if graph:
@@ -117,6 +124,10 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
             evs[0].record(stream)
         if g is not None:
             g.replay()
+            if evs:
+                evs[1].record(stream)
+        elif fused:
+            load_and_match()
             if evs:
                 evs[1].record(stream)
         else:
@@ -143,6 +154,20 @@ def run_gpu(w, prec, steps, warmup, block_size=0, search_lanes=0, graph=False, d
     t_match = [e[1].elapsed_time(e[2]) for e in evs]
     t_step = [e[0].elapsed_time(e[2]) for e in evs]
     ktimes = m.kernel_times() if not graph else []
+    if fused and not graph:
+        # the fused call has no boundary between binning and matching: the
+        # split comes from separate calls after the timed steps
+        sp = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(min(steps, 10))]
+        for e in sp:
+            e[0].record(stream)
+            m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+            e[1].record(stream)
+            m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        m.kernel_times()
+        t_bin = [e[0].elapsed_time(e[1]) for e in sp]
+        t_match = [e[1].elapsed_time(e[2]) for e in sp]
     if graph:
         # a replayed graph has no event between its kernels: the match
         # kernel's own duration comes from a matcher with the same launch
@@ -425,6 +450,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparator")
     ap.add_argument("--graph", action="store_true", help="replay bin + match as one captured graph")
+    ap.add_argument("--separate", action="store_true",
+                    help="time trd_load_tracklets + trd_match instead of the one trd_load_and_match call")
     ap.add_argument("--n-hyp", type=int, default=0,
                     help="hypotheses kept per layer (0: the single best candidate)")
     ap.add_argument("--chi2-penalty", type=float, default=None,
@@ -496,7 +523,8 @@ def main():
         del d
     from paper_2003_03174_amd import binding
     r = run_gpu(w, args.precision, args.steps, args.warmup, args.block_size, args.search_lanes,
-                graph=args.graph, flags=binding.TRD_CFG_PERSISTENT if args.persistent else 0)
+                graph=args.graph, flags=binding.TRD_CFG_PERSISTENT if args.persistent else 0,
+                fused=not args.separate)
     ms = r["wall_ms_per_step"]
     split = r["match_ms"] is not None
     match_avg = sum(r["match_ms"]) / len(r["match_ms"]) if split else None
@@ -536,10 +564,14 @@ def main():
             "persistent": bool(args.persistent),
             "n_hyp": args.n_hyp,
             "chi2_penalty": P.get("chi2_penalty") if args.n_hyp else None,
-            "step": "bin all tracklets + match all tracks",
+            "step": "bin all tracklets + match all tracks"
+                    + (" (trd_load_tracklets + trd_match)" if args.separate else
+                       " (trd_load_and_match: the seeds are ordered while the tracklets are binned)"),
         },
         "latency_ms": {"step_p50": pct(r["step_ms"], 50), "step_p99": pct(r["step_ms"], 99),
-                       "bin_avg": bin_avg, "match_avg": match_avg, "match_kernel_avg": kernel_avg},
+                       "bin_avg": bin_avg, "match_avg": match_avg, "match_kernel_avg": kernel_avg,
+                       "split_from": None if (args.separate or args.graph) else
+                       "separate trd_load_tracklets + trd_match calls after the timed steps"},
         "tracks_ge2_matches_per_s": r["n_ge2"] / (ms * 1e-3),
         "refit": {"ms": sum(r["refit_ms"]) / len(r["refit_ms"]),
                   "tracks_per_s": n / (sum(r["refit_ms"]) / len(r["refit_ms"]) * 1e-3),

@@ -291,6 +291,17 @@ typedef struct trd_refit_out {
     uint32_t *status;  /* [n] TRD_TRK_* bits of the refit */
 } trd_refit_out;
 
+/* trd_load_tracklets followed by trd_match on the same stream (the search
+ * of Sect. 3 over one batch of tracklets and seeds), with the same results,
+ * but the seeds' processing order is computed on a stream of the context
+ * while the tracklets are binned (the two are independent), joined before
+ * the match.  Both inputs must be ready on hip_stream when it is called.
+ * Arguments and errors as of the two calls (checked before anything is
+ * enqueued); capturable into a graph like them (the fork is joined back
+ * into hip_stream). */
+int trd_load_and_match(trd_ctx *ctx, const trd_tracklets *t, int64_t n_tkl, int32_t n_groups,
+                       const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream);
+
 /* TRD-only refit of matched tracks (Sect. 2, step 3: a refit from the outer
  * detectors in which the TPC information is ignored).  For each track: the
  * state of trd_match with its covariance replaced by diag(refit_cov), then

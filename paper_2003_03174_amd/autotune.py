@@ -74,8 +74,8 @@ def _time_step(params, d, n_groups, precision, bs, lanes, flags, reps):
     for r in range(reps + 1):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], n_groups)
-        m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+        m.load_and_match(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], n_groups, d["p"], d["cov"], d["x"],
+                         d["sector"], tgroup=d["group"], out=out)
         e1.record(stream)
         torch.cuda.synchronize()
         if r:

@@ -35,7 +35,8 @@ TRD_CFG_INPUT_ORDER = 8
 TRD_CFG_TIME_KERNEL = 16
 
 # every symbol include/trd.h declares
-EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_match_noalloc", "trd_refit",
+EXPORTS = ("trd_create", "trd_reserve", "trd_load_tracklets", "trd_match", "trd_match_noalloc",
+           "trd_load_and_match", "trd_refit",
            "trd_residual_sums",
            "trd_voxel_solve", "trd_get_binning", "trd_copy_binning", "trd_device_bytes", "trd_kernel_times",
            "trd_destroy", "trd_status_string")
@@ -124,6 +125,8 @@ def lib():
         L.trd_load_tracklets.argtypes = [vp, C.POINTER(trd_tracklets), C.c_int64, C.c_int32, vp]
         L.trd_match.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
         L.trd_match_noalloc.argtypes = [vp, C.POINTER(trd_tracks), C.c_int64, C.POINTER(trd_results), vp]
+        L.trd_load_and_match.argtypes = [vp, C.POINTER(trd_tracklets), C.c_int64, C.c_int32, C.POINTER(trd_tracks),
+                                         C.c_int64, C.POINTER(trd_results), vp]
         L.trd_refit.argtypes = [vp, C.POINTER(trd_refit_in), C.POINTER(trd_tracklets), C.c_int64, C.c_int64,
                                 C.POINTER(trd_refit_out), vp]
         L.trd_residual_sums.argtypes = [vp, C.POINTER(trd_reference), C.POINTER(trd_tpc_clusters), C.c_int64,
@@ -213,6 +216,11 @@ def trd_reserve(ctx, max_tracklets, max_groups, max_tracks):
 def trd_load_tracklets(ctx, t: trd_tracklets, n, n_groups, stream=0):
     _check(lib().trd_load_tracklets(ctx, C.byref(t), int(n), int(n_groups), stream or None),
            "trd_load_tracklets")
+
+
+def trd_load_and_match(ctx, t: trd_tracklets, n_tkl, n_groups, trk: trd_tracks, n, res: trd_results, stream=0):
+    _check(lib().trd_load_and_match(ctx, C.byref(t), int(n_tkl), int(n_groups), C.byref(trk), int(n),
+                                    C.byref(res), stream or None), "trd_load_and_match")
 
 
 def trd_match(ctx, trk: trd_tracks, n, res: trd_results, stream=0):
@@ -354,6 +362,31 @@ class Matcher:
         res = trd_results(*(None if out[k] is None else out[k].data_ptr() for k in
                             ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status")))
         (trd_match_noalloc if noalloc else trd_match)(self.ctx, trk, n, res, _stream_handle(stream))
+        return out
+
+    def load_and_match(self, y, z, dy, det_row, group, n_groups, p, cov, x, sector, tgroup=None, out=None,
+                       stream=None):
+        """load() then match() in one trd_load_and_match call (the seeds are
+        ordered while the tracklets are binned); `group` the tracklets'
+        groups, `tgroup` the tracks'."""
+        n = int(x.numel())
+        for t in (y, z, dy, det_row) + ((group,) if group is not None else ()):
+            assert t.is_cuda and t.is_contiguous()
+        for t in (p, cov, x):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == self.fdtype
+        assert sector.is_cuda and sector.is_contiguous()
+        self._keep_in = (y, z, dy, det_row, group)
+        if out is None:
+            out = self.alloc_results(n)
+        tk = trd_tracklets(y.data_ptr(), z.data_ptr(), dy.data_ptr(), det_row.data_ptr(),
+                           group.data_ptr() if group is not None else None)
+        trk = trd_tracks(p.data_ptr(), cov.data_ptr(), x.data_ptr(), sector.data_ptr(),
+                         tgroup.data_ptr() if tgroup is not None else None)
+        res = trd_results(*(None if out[k] is None else out[k].data_ptr() for k in
+                            ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status")))
+        trd_load_and_match(self.ctx, tk, y.numel(), n_groups, trk, n, res, _stream_handle(stream))
+        self.n_tracklets = int(y.numel())
+        self.n_groups = int(n_groups)
         return out
 
     def refit(self, matched, y, z, det_row, stream=None):

@@ -38,6 +38,11 @@ struct trd_ctx {
     uint32_t *d_trank = nullptr, *d_thist = nullptr, *d_thist_off = nullptr, *d_ttiles = nullptr;
     unsigned char *d_rows_in = nullptr, *d_rows_out = nullptr;
 
+    // trd_load_and_match: a stream of the context (default priority) that runs
+    // the seeds' ordering beside the binning, and the events of its fork and join
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+
     // TRD_CFG_TIME_KERNEL: a ring of event pairs around the main match kernel
     static constexpr int kEvRing = 64;
     hipEvent_t ev[kEvRing][2] = {};
@@ -447,6 +452,12 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out)
     }
     if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->n_cu = 1;
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
+        trd_destroy(ctx);
+        return TRD_EDEVICE;
+    }
     if (cfg->flags & TRD_CFG_TIME_KERNEL) {
         for (int k = 0; k < trd_ctx::kEvRing; k++)
             if (hipEventCreate(&ctx->ev[k][0]) != hipSuccess || hipEventCreate(&ctx->ev[k][1]) != hipSuccess) {
@@ -475,18 +486,25 @@ int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t
     return hip_status(hipDeviceSynchronize());
 }
 
-int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t n_groups,
-                       void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+int load_check(const trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t n_groups)
 {
     if (!ctx || !t || n < 0 || n_groups < 1) return TRD_EINVAL;
     if (n > 0 && (!t->y || !t->z || !t->dy || !t->det_row)) return TRD_EINVAL;
     if (n >= (int64_t)INT32_MAX) return TRD_EINVAL;
     const int64_t nc = n_cells_of(ctx->cfg, n_groups);
     if (nc >= (int64_t)UINT32_MAX - 1) return TRD_EINVAL;
-    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
-    hipStream_t s = (hipStream_t)hip_stream;
+    return TRD_OK;
+}
+
+// Buffers of the binning, then its kernels on s (arguments checked).
+int load_enqueue(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t n_groups, hipStream_t s)
+{
+    const int64_t nc = n_cells_of(ctx->cfg, n_groups);
     int rc;
-    if ((rc = pending_status(s))) return rc;
     if ((rc = ensure_tkl(ctx, n)) || (rc = ensure_cells(ctx, nc))) return rc;
     BinCfg b = ctx->gd.bin;
     b.n_groups = n_groups;
@@ -512,6 +530,21 @@ int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t 
     return TRD_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int trd_load_tracklets(trd_ctx *ctx, const trd_tracklets *t, int64_t n, int32_t n_groups,
+                       void *hip_stream)
+{
+    int rc;
+    if ((rc = load_check(ctx, t, n, n_groups))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = pending_status(s))) return rc;
+    return load_enqueue(ctx, t, n, n_groups, s);
+}
+
 }  // extern "C"
 
 namespace {
@@ -520,24 +553,34 @@ namespace {
 // re-run queue and the counters come from that scratch, the tracks are
 // matched in the caller's order and nothing is allocated; otherwise the
 // context's buffers are used (grown as needed).
-int match_impl(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream,
-               uint32_t *fixed)
+int match_check(const trd_tracks *in, int64_t n, const trd_results *out)
 {
-    if (!ctx || !in || !out || n < 0) return TRD_EINVAL;
-    if (!ctx->loaded) return TRD_ESTATE;
+    if (!in || !out || n < 0) return TRD_EINVAL;
     if (n == 0) return TRD_OK;
     if (n >= (int64_t)INT32_MAX) return TRD_EINVAL;
     if (!in->p || !in->cov || !in->x || !in->sector || !out->idx || !out->p || !out->cov ||
         !out->x || !out->sector || !out->chi2 || !out->n_match || !out->status)
         return TRD_EINVAL;
-    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    return TRD_OK;
+}
+
+// A match call in parts: prepare (buffers, arguments of the kernels; `ord`:
+// the call runs in the spatial order of the seeds of n_groups groups), the
+// ordering of the seeds (sort and pack), and the match itself.
+struct MatchCall {
+    MatchIO io{};
+    TrackOrder ob{};
+    bool ord = false;
+};
+
+int match_prepare(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, int32_t n_groups,
+                  uint32_t *fixed, MatchCall &mc)
+{
     int rc;
-    const hipStream_t s = (hipStream_t)hip_stream;
-    if ((rc = pending_status(s))) return rc;
-    const bool ord = !fixed && ordered(ctx->cfg) && ctx->n_groups < kMaxOrderGroups;
+    mc.ord = !fixed && ordered(ctx->cfg) && n_groups < kMaxOrderGroups;
     if (!fixed && (ctx->cfg.precision == TRD_PREC_FP32 || ordered(ctx->cfg)) && (rc = ensure_trk(ctx, n)))
         return rc;
-    MatchIO io{};
+    MatchIO &io = mc.io;
     io.sorted = ctx->d_sorted;
     io.offsets = ctx->d_offsets;
     io.ip = in->p;
@@ -562,28 +605,53 @@ int match_impl(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, 
     io.force_fallback = (ctx->cfg.flags & TRD_CFG_FORCE_FALLBACK) ? 1 : 0;
     io.work_next = counters + 2;
     io.work_done = counters + 3;
+    if (mc.ord)
+        mc.ob = TrackOrder{ctx->d_tkey_a, ctx->d_tkey_b, ctx->d_tval_a, ctx->d_tval_b, ctx->d_trank,
+                           ctx->d_thist, ctx->d_thist_off, ctx->d_ttiles, ctx->d_rows_in, ctx->d_rows_out};
+    return TRD_OK;
+}
+
+void match_order(trd_ctx *ctx, MatchCall &mc, int32_t n_groups, hipStream_t s)
+{
+    if (mc.ord) launch_order_in(ctx->cfg.precision, mc.io, n_groups, mc.ob, s);
+}
+
+int match_run(trd_ctx *ctx, MatchCall &mc, uint32_t *fixed, hipStream_t s)
+{
+    MatchIO &io = mc.io;
     // the shared scratch keeps the last call's contents: the counters start
     // at zero (a fill kernel, also under stream capture)
-    if (fixed) launch_fill_u32(counters, 0u, 4, s);
+    if (fixed) launch_fill_u32(fixed, 0u, 4, s);
     if (ctx->cfg.flags & TRD_CFG_TIME_KERNEL) {
         const int slot = (int)(ctx->ev_count % trd_ctx::kEvRing);
         io.ev_begin = ctx->ev[slot][0];
         io.ev_end = ctx->ev[slot][1];
         ctx->ev_count++;
     }
-    TrackOrder ord_buf{};
-    if (ord) {
-        ord_buf = TrackOrder{ctx->d_tkey_a, ctx->d_tkey_b, ctx->d_tval_a, ctx->d_tval_b, ctx->d_trank,
-                             ctx->d_thist, ctx->d_thist_off, ctx->d_ttiles, ctx->d_rows_in, ctx->d_rows_out};
-        launch_order_in(ctx->cfg.precision, io, ctx->n_groups, ord_buf, s);
-    }
     if (ctx->cfg.n_hyp > 0)
         launch_beam(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.n_hyp, s);
     else
         launch_match(ctx->cfg.precision, ctx->gd, ctx->gf, io, ctx->cfg.block_size, ctx->cfg.search_lanes,
                      (ctx->cfg.flags & TRD_CFG_PERSISTENT) != 0, ctx->n_cu, s);
-    if (ord) launch_order_out(ctx->cfg.precision, io, ord_buf, s);
+    if (mc.ord) launch_order_out(ctx->cfg.precision, io, mc.ob, s);
     return launch_status();
+}
+
+int match_impl(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream,
+               uint32_t *fixed)
+{
+    if (!ctx) return TRD_EINVAL;
+    int rc;
+    if ((rc = match_check(in, n, out))) return rc;
+    if (!ctx->loaded) return TRD_ESTATE;
+    if (n == 0) return TRD_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = pending_status(s))) return rc;
+    MatchCall mc;
+    if ((rc = match_prepare(ctx, in, n, out, ctx->n_groups, fixed, mc))) return rc;
+    match_order(ctx, mc, ctx->n_groups, s);
+    return match_run(ctx, mc, fixed, s);
 }
 
 }  // namespace
@@ -602,6 +670,35 @@ int trd_match_noalloc(trd_ctx *ctx, const trd_tracks *in, int64_t n, trd_results
     uint32_t *sc = scratch_of(ctx->device);
     if (!sc) return ctx->device >= kMaxScratchDevices ? TRD_EINVAL : TRD_EDEVICE;
     return match_impl(ctx, in, n, out, hip_stream, sc);
+}
+
+int trd_load_and_match(trd_ctx *ctx, const trd_tracklets *t, int64_t n_tkl, int32_t n_groups,
+                       const trd_tracks *in, int64_t n, trd_results *out, void *hip_stream)
+{
+    int rc;
+    if ((rc = load_check(ctx, t, n_tkl, n_groups)) || (rc = match_check(in, n, out))) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TRD_EDEVICE;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = pending_status(s))) return rc;
+    // every buffer first: the match reads the binning's at their final place
+    if ((rc = ensure_tkl(ctx, n_tkl)) || (rc = ensure_cells(ctx, n_cells_of(ctx->cfg, n_groups)))) return rc;
+    MatchCall mc;
+    if (n > 0 && (rc = match_prepare(ctx, in, n, out, n_groups, nullptr, mc))) return rc;
+    // the seeds' order on the side stream, from the point where the caller's
+    // inputs are ready, beside the binning
+    const bool fork = n > 0 && mc.ord;
+    if (fork && (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
+                 hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess))
+        return TRD_EDEVICE;
+    if (fork) match_order(ctx, mc, n_groups, ctx->side);
+    if (fork && (hipEventRecord(ctx->join_ev, ctx->side) != hipSuccess || (rc = launch_status())))
+        return rc ? rc : TRD_EDEVICE;
+    // the stream joins the side stream before anything can fail, so that a
+    // captured fork is always joined
+    rc = load_enqueue(ctx, t, n_tkl, n_groups, s);
+    if (fork && hipStreamWaitEvent(s, ctx->join_ev, 0) != hipSuccess) return TRD_EDEVICE;
+    if (rc || n == 0) return rc;
+    return match_run(ctx, mc, nullptr, s);
 }
 
 int trd_refit(trd_ctx *ctx, const trd_refit_in *in, const trd_tracklets *tkl, int64_t n_tkl, int64_t n,
@@ -746,6 +843,9 @@ void trd_destroy(trd_ctx *ctx)
     for (int k = 0; k < trd_ctx::kEvRing; k++)
         for (int e = 0; e < 2; e++)
             if (ctx->ev[k][e]) (void)hipEventDestroy(ctx->ev[k][e]);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 

@@ -355,9 +355,9 @@ class HipExecutor:
             S["din"][:nb_in].copy_(src[:nb_in], non_blocking=True)
             dv = self._views(S["din"], lay_in)
             ev0.record(s)
-            m.load(dv["y"], dv["z"], dv["dy"], dv["det_row"], dv["tgroup"], len(frames), stream=s)
             out = self._views(S["dout"], lay_out)
-            m.match(dv["p"], dv["cov"], dv["x"], dv["sector"], dv["group"], out=out, stream=s)
+            m.load_and_match(dv["y"], dv["z"], dv["dy"], dv["det_row"], dv["tgroup"], len(frames), dv["p"],
+                             dv["cov"], dv["x"], dv["sector"], tgroup=dv["group"], out=out, stream=s)
             ev1.record(s)
             S["hout"][:nb_out].copy_(S["dout"][:nb_out], non_blocking=True)
             done.record(s)

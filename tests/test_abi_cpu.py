@@ -96,6 +96,8 @@ def test_null_context_calls():
     assert L.trd_load_tracklets(None, C.byref(t), 0, 1, None) == B.TRD_EINVAL
     assert L.trd_match(None, C.byref(B.trd_tracks()), 0, C.byref(B.trd_results()), None) == B.TRD_EINVAL
     assert L.trd_match_noalloc(None, C.byref(B.trd_tracks()), 0, C.byref(B.trd_results()), None) == B.TRD_EINVAL
+    assert L.trd_load_and_match(None, C.byref(t), 0, 1, C.byref(B.trd_tracks()), 0, C.byref(B.trd_results()),
+                                None) == B.TRD_EINVAL
     assert L.trd_reserve(None, 1, 1, 1) == B.TRD_EINVAL
     assert L.trd_device_bytes(None) == 0
     L.trd_destroy(None)
