@@ -29,6 +29,10 @@ constexpr int kBins = 1 << kRadixBits;          // 256 digit values
 constexpr int kSub = 8;                         // sub-tiles of 256 elements per block
 constexpr int kSortTile = kBlock * kSub;        // elements per radix workgroup
 constexpr int kWideBits = 11;                   // widest digit of the tracklet partition
+// threads of its workgroups (tiles of kSub * that many elements): 256 for a
+// 10-bit digit, 512 for an 11-bit one (twice the elements per digit and tile;
+// 64-frame step 1.45 -> 1.37 ms, while the 10-bit pass of one group loses 5 µs)
+template <int kBits> constexpr int kWideThreads = kBits <= 10 ? 256 : 512;
 
 __global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
 {
@@ -190,20 +194,21 @@ struct SlotPassSrc {
 };
 
 // digit histogram of one tile, stored digit-major: hist[d * n_blocks + block]
-// (only the first nd digits are stored: the ones that occur)
-template <typename Src, int kBits>
-__global__ void __launch_bounds__(kBlock)
+// (only the first nd digits are stored: the ones that occur); tiles of
+// kSub * kThreads elements
+template <typename Src, int kBits, int kThreads = kBlock>
+__global__ void __launch_bounds__(kThreads)
     k_radix_hist(Src src, int64_t n, int shift, int nd, uint32_t *__restrict__ hist, uint32_t *__restrict__ key_out)
 {
     constexpr int kNb = 1 << kBits;
     __shared__ uint32_t h[kNb];
-    for (int d = threadIdx.x; d < kNb; d += kBlock) h[d] = 0;
+    for (int d = threadIdx.x; d < kNb; d += kThreads) h[d] = 0;
     __syncthreads();
     const unsigned tile = xcd_tile();
-    const int64_t base = (int64_t)tile * kSortTile;
+    const int64_t base = (int64_t)tile * (kSub * kThreads);
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
-        const int64_t e = base + j * kBlock + threadIdx.x;
+        const int64_t e = base + j * kThreads + threadIdx.x;
         if (e < n) {
             const uint32_t k = src.key(e);
             if (key_out) key_out[e] = k;
@@ -211,7 +216,7 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < nd; d += kBlock) hist[(int64_t)d * gridDim.x + tile] = h[d];
+    for (int d = threadIdx.x; d < nd; d += kThreads) hist[(int64_t)d * gridDim.x + tile] = h[d];
 }
 
 // Stable scatter of one tile: elements are taken in input order (sub-tile,
@@ -316,29 +321,29 @@ __global__ void __launch_bounds__(kBlock)
 // there is nothing to gain from regrouping the tile in LDS before the
 // stores, so each lane stores its element directly (and the small LDS
 // footprint keeps many workgroups resident).
-template <typename Src, int kBits>
-__global__ void __launch_bounds__(kBlock)
+template <typename Src, int kBits, int kThreads>
+__global__ void __launch_bounds__(kThreads)
     k_wide_scatter(Src src, int64_t n, int shift, int nd, const uint32_t *__restrict__ hist_off,
                    uint32_t *__restrict__ keys_out, typename Src::Rec *__restrict__ recs_out)
 {
     using Rec = typename Src::Rec;
-    constexpr int kNb = 1 << kBits, kWaves = kBlock / 64;
+    constexpr int kNb = 1 << kBits, kWaves = kThreads / 64;
     __shared__ uint32_t glob[kNb];         // next global position of each digit for this tile
     __shared__ uint16_t wc[kWaves][kNb];   // per wavefront of the current sub-tile: count of each digit
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const unsigned tile = xcd_tile();
-    for (int d = tid; d < kNb; d += kBlock) {
+    for (int d = tid; d < kNb; d += kThreads) {
         glob[d] = d < nd ? hist_off[(int64_t)d * gridDim.x + tile] : 0u;
 #pragma unroll
         for (int w = 0; w < kWaves; w++) wc[w][d] = 0;
     }
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)tile * kSortTile;
+    const int64_t base = (int64_t)tile * (kSub * kThreads);
     uint32_t kv[kSub];
     Rec rv[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
-        const int64_t e = base + j * kBlock + tid;
+        const int64_t e = base + j * kThreads + tid;
         kv[j] = 0;
         rv[j] = Rec{};
         if (e < n) src.load(e, kv[j], rv[j]);
@@ -346,7 +351,7 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
-        const bool valid = base + j * kBlock + tid < n;
+        const bool valid = base + j * kThreads + tid < n;
         const uint32_t d = (src.sort_key(kv[j]) >> shift) & (kNb - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -694,6 +699,7 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
 
 int64_t scan_block_sums_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 int64_t radix_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+static int64_t wide_blocks(int64_t n, int threads) { return (n + kSub * threads - 1) / (kSub * threads); }
 int64_t tkl_hist_len(int64_t n) { return radix_blocks(n > 0 ? n : 1) * (int64_t)(1 << kWideBits); }
 
 // exclusive sum scan of n values (out may alias nothing of in)
@@ -727,13 +733,14 @@ template <int kBits>
 static void wide_pass_tkl(TklSrc src, int64_t n, int nd, uint32_t *key_cache, uint32_t *hist, uint32_t *hist_off,
                           uint32_t *tiles, uint32_t *keys_out, float4 *recs_out, hipStream_t s)
 {
-    const int64_t nblk = radix_blocks(n);
+    constexpr int kT = kWideThreads<kBits>;
+    const int64_t nblk = wide_blocks(n, kT);
     src.cached = nullptr;
-    hipLaunchKernelGGL((k_radix_hist<TklSrc, kBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, nd,
-                       hist, key_cache);
+    hipLaunchKernelGGL((k_radix_hist<TklSrc, kBits, kT>), dim3((unsigned)nblk), dim3(kT), 0, s, src, n, 0, nd, hist,
+                       key_cache);
     launch_excl_scan(hist, nblk * nd, tiles, hist_off, s);
     src.cached = key_cache;
-    hipLaunchKernelGGL((k_wide_scatter<TklSrc, kBits>), dim3((unsigned)nblk), dim3(kBlock), 0, s, src, n, 0, nd,
+    hipLaunchKernelGGL((k_wide_scatter<TklSrc, kBits, kT>), dim3((unsigned)nblk), dim3(kT), 0, s, src, n, 0, nd,
                        hist_off, keys_out, recs_out);
 }
 
@@ -797,7 +804,7 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
     // the first tile (hist_off[b * tiles]); otherwise the starts are found
     // from the partitioned keys.
     const uint32_t *bnd = buf.hist_off;
-    int64_t bstride = radix_blocks(n);
+    int64_t bstride = wide_blocks(n, wide == 10 ? kWideThreads<10> : kWideThreads<kWideBits>);
     if (n == 0 || passes > 1) {
         hipLaunchKernelGGL(k_slot_bounds, dim3(grid_for(n + 1, kBlock)), dim3(kBlock), 0, s, buf.keys_a, n, slot,
                            n_slots + 2, buf.bstart);
