@@ -795,17 +795,13 @@ __device__ __forceinline__ void scan_road_lane(const Road<TS> &R, const DevCfg<T
     }
 }
 
-// Gate one record of stack st (chamber shifted by dxd in x when kShift) and
-// offer it to the accumulator unless `in` is false.
-template <bool kShift, typename TS, typename A>
+// Gate one record of stack st (its chamber shifted by dxd in x) and offer it
+// to the accumulator unless `in` is false.
+template <typename TS, typename A>
 __device__ __forceinline__ void gate_record(const Road<TS> &R, const DevCfg<TS> &g, const float4 &rec,
                                             int st, TS dxd, bool in, A &acc)
 {
-    TS ye = R.y, ze = R.z;
-    if (kShift) {
-        ye = R.y + dxd * R.tphi;
-        ze = R.z + dxd * R.tz;
-    }
+    const TS ye = R.y + dxd * R.tphi, ze = R.z + dxd * R.tz;
     bool pass;
     const TS c = cand_chi2(R, ye, ze, rec, g.chi2_max, pass);
     acc.offer(c, __float_as_int(rec.w), rec.x, rec.z, st, pass & in);
@@ -814,16 +810,17 @@ __device__ __forceinline__ void gate_record(const Road<TS> &R, const DevCfg<TS> 
 // One lane walks a whole road with its records flattened: the bounds of up
 // to kBatch ranges come in one memory round trip, then their records are
 // taken kU at a time across range boundaries, so a round trip fetches kU
-// records however the road's candidates fall into cells.  kShift: chambers
-// are shifted in x (misalignment), so each record's stack moves the
-// track's point.
-template <bool kShift, typename TS, typename A>
-__device__ __forceinline__ void scan_road_flat_k(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
-                                                 A &B)
+// records however the road's candidates fall into cells.  (One walk for
+// shifted and unshifted chambers: a second copy specialised for chambers
+// without shifts made the kernel 3-7 % slower.)
+template <typename TS, typename A>
+__device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
+                                               A &B)
 {
     constexpr int kBatch = 4, kU = 4;
     const int nr = g.bin.n_rows;
     const RangeGrid q = range_grid(R, nr);
+    const bool shifted = g.dx_max != TS(0);
     // Cell index of the first pad row of range (is, id, iy), kept as a running
     // sum: one y bin further adds sy, the next dy bin (y back to the first)
     // adds sy + wy, the next stack (dy and y back to the first) adds ws on top
@@ -885,22 +882,13 @@ __device__ __forceinline__ void scan_road_flat_k(const Road<TS> &R, const DevCfg
                     su[u] = past ? st[q] : su[u];
                 }
                 rec[u] = io.sorted[k];
-                dxd[u] = kShift ? g.dx[R.sdet0 + su[u] * kLayers] : TS(0);
+                dxd[u] = TS(0);
+                if (shifted) dxd[u] = g.dx[R.sdet0 + su[u] * kLayers];
             }
 #pragma unroll
-            for (int u = 0; u < kU; u++) gate_record<kShift>(R, g, rec[u], su[u], dxd[u], in[u], B);
+            for (int u = 0; u < kU; u++) gate_record(R, g, rec[u], su[u], dxd[u], in[u], B);
         }
     }
-}
-
-template <typename TS, typename A>
-__device__ __forceinline__ void scan_road_flat(const Road<TS> &R, const DevCfg<TS> &g, const MatchIO &io,
-                                               A &B)
-{
-    if (g.dx_max != TS(0))
-        scan_road_flat_k<true>(R, g, io, B);
-    else
-        scan_road_flat_k<false>(R, g, io, B);
 }
 
 // G lanes share a road: lane `sub` takes every G-th range.
