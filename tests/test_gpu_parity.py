@@ -114,6 +114,34 @@ def test_cells_per_chamber_above_one_chunk():
     assert rep.ok, rep.summary()
 
 
+def test_unaligned_tracklet_arrays():
+    """Tracklet arrays at an offset of one element (not 16-byte aligned):
+    binning bit-exact, parity."""
+    w = workload("c1_small_fp64")
+    lay = synth.to_device_layout(w)
+    d = B.device_inputs(lay, "fp32")
+    m = B.Matcher(w["params"], "fp32")
+    shifted = {}
+    for k in ("y", "z", "dy", "det_row", "tgroup"):
+        buf = torch.empty(d[k].numel() + 1, dtype=d[k].dtype, device=d[k].device)
+        buf[1:].copy_(d[k])
+        shifted[k] = buf[1:]
+    assert shifted["y"].data_ptr() % 16 != 0
+    m.load(shifted["y"], shifted["z"], shifted["dy"], shifted["det_row"], shifted["tgroup"], w["n_groups"])
+    out = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    torch.cuda.synchronize()
+    res = pu.to_numpy(out)
+    off, srt = m.binning()
+    torch.cuda.synchronize()
+    res["offsets"] = off.cpu().numpy().view(np.uint32)
+    res["sorted"] = srt.cpu().numpy()
+    m.close()
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    rep = pu.compare(ref, res, "fp32")
+    assert rep.ok, rep.summary()
+
+
 def test_cells_per_bucket_above_one_chunk():
     """A chamber of 1 cm y bins x 1/16 cm dy bins x 18 rows (294912 cells):
     the cell sort goes over 18 LDS chunks: binning bit-exact, parity."""
