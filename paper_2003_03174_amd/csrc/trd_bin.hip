@@ -63,17 +63,21 @@ __device__ __forceinline__ void wave_sync()
 __device__ __forceinline__ uint32_t cell_key(float y, float z, float dy, uint32_t det_row,
                                              int32_t grp, const BinCfg &b)
 {
+    // without branches (the absent-slot mask is read at an index kept in
+    // bounds), so that the loads of several tracklets can be in flight at once
     const uint32_t det = det_row >> 5, row = det_row & 31u;
-    if (det >= (uint32_t)kDet || row >= (uint32_t)b.n_rows || grp < 0 || grp >= b.n_groups ||
-        !__builtin_isfinite(y) || !__builtin_isfinite(z) || !__builtin_isfinite(dy) || slot_absent(b, (int)det))
-        return b.n_cells;
-    // bins in double: the float value widened, a power-of-two scale, floor
-    const double u = floor(((double)y - b.y_min) * b.inv_w);
-    const int yb = !(u >= 0.0) ? 0 : (u > (double)(b.n_yb - 1) ? b.n_yb - 1 : (int)u);
-    const double v = floor(((double)dy - b.dy_min) * b.inv_wd);
-    const int db = !(v >= 0.0) ? 0 : (v > (double)(b.n_db - 1) ? b.n_db - 1 : (int)v);
-    return ((((uint32_t)grp * kDet + det) * (uint32_t)b.n_db + (uint32_t)db) * (uint32_t)b.n_yb +
-            (uint32_t)yb) * (uint32_t)b.n_rows + row;
+    const bool drop = (det >= (uint32_t)kDet) | (row >= (uint32_t)b.n_rows) | (grp < 0) | (grp >= b.n_groups) |
+                      !__builtin_isfinite(y) | !__builtin_isfinite(z) | !__builtin_isfinite(dy) |
+                      slot_absent(b, det < (uint32_t)kDet ? (int)det : 0);
+    // bins in double: the float value widened, a power-of-two scale, floor,
+    // clamped to the first and last bin (fmax takes 0 for a NaN)
+    const double u = fmin(fmax(floor(((double)y - b.y_min) * b.inv_w), 0.0), (double)(b.n_yb - 1));
+    const double v = fmin(fmax(floor(((double)dy - b.dy_min) * b.inv_wd), 0.0), (double)(b.n_db - 1));
+    const uint32_t yb = (uint32_t)(int)u, db = (uint32_t)(int)v;
+    const uint32_t k = ((((uint32_t)grp * kDet + det) * (uint32_t)b.n_db + db) * (uint32_t)b.n_yb + yb) *
+                           (uint32_t)b.n_rows + row;
+    const uint32_t m = 0u - (uint32_t)drop;
+    return (k & ~m) | (b.n_cells & m);
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
@@ -123,24 +127,26 @@ struct KeyDiv {
 // sort_key(key).  First pass of the tracklet partition: the caller's
 // arrays, key and record computed on the fly, sorted by bucket.
 // Later passes: the previous pass's keys and records.
+// kGrouped: a group per tracklet in grp (else every tracklet is in group 0
+// and grp is not read); a compile-time choice, so that no load is behind a branch
+template <bool kGrouped>
 struct TklSrc {
     const float *y, *z, *dy;
     const uint32_t *det_row;
     const int32_t *grp;
     BinCfg b;
     KeyDiv slot;
-    const uint32_t *cached;  // keys written by the histogram pass (null there)
+    const uint32_t *cached;  // keys written by the histogram pass, read by the scatter
     using Rec = float4;
     __device__ __forceinline__ uint32_t sort_key(uint32_t k) const { return slot(k); }
     __device__ __forceinline__ uint32_t key(int64_t e) const
     {
-        return cell_key(y[e], z[e], dy[e], det_row[e], grp ? grp[e] : 0, b);
+        return cell_key(y[e], z[e], dy[e], det_row[e], kGrouped ? grp[e] : 0, b);
     }
     __device__ __forceinline__ void load(int64_t e, uint32_t &k, float4 &rec) const
     {
-        const float ye = y[e], ze = z[e], dye = dy[e];
-        k = cached ? cached[e] : cell_key(ye, ze, dye, det_row[e], grp ? grp[e] : 0, b);
-        rec = make_float4(ye, dye, ze, __int_as_float((int)e));
+        k = cached[e];
+        rec = make_float4(y[e], dy[e], z[e], __int_as_float((int)e));
     }
 };
 
@@ -206,13 +212,20 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
     const unsigned tile = xcd_tile();
     const int64_t base = (int64_t)tile * (kSub * kThreads);
+    // keys from clamped indexes (n > 0), so that the loads of every
+    // sub-tile are in flight together; only the counting is guarded
+    uint32_t kv[kSub];
+#pragma unroll
+    for (int j = 0; j < kSub; j++) {
+        const int64_t e = base + j * kThreads + threadIdx.x;
+        kv[j] = src.key(e < n ? e : n - 1);
+    }
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
         const int64_t e = base + j * kThreads + threadIdx.x;
         if (e < n) {
-            const uint32_t k = src.key(e);
-            if (key_out) key_out[e] = k;
-            atomicAdd(&h[(src.sort_key(k) >> shift) & (kNb - 1)], 1u);
+            if (key_out) key_out[e] = kv[j];
+            atomicAdd(&h[(src.sort_key(kv[j]) >> shift) & (kNb - 1)], 1u);
         }
     }
     __syncthreads();
@@ -339,14 +352,14 @@ __global__ void __launch_bounds__(kThreads)
     }
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)tile * (kSub * kThreads);
+    // clamped indexes (n > 0): every load in flight at once; the lanes
+    // past the end take no part below
     uint32_t kv[kSub];
     Rec rv[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
         const int64_t e = base + j * kThreads + tid;
-        kv[j] = 0;
-        rv[j] = Rec{};
-        if (e < n) src.load(e, kv[j], rv[j]);
+        src.load(e < n ? e : n - 1, kv[j], rv[j]);
     }
     __syncthreads();
 #pragma unroll
@@ -493,11 +506,18 @@ __global__ void __launch_bounds__(kOrderBlock)
         for (uint32_t i = tid; i < cn; i += kOrderBlock) cur[i] = 0;
         __syncthreads();
         for (uint32_t b0 = start; b0 < end; b0 += kSeg) {
+            // loads from a clamped index, all in flight at once (a guarded
+            // load would wait for its data before the next one is issued)
             uint32_t lk[kOrderSub];
 #pragma unroll
             for (int u = 0; u < kOrderSub; u++) {
                 const uint32_t e = b0 + u * kOrderBlock + tid;
-                lk[u] = e < end ? keys[e] - kb : cn;
+                lk[u] = keys[e < end ? e : end - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kOrderSub; u++) {
+                const uint32_t e = b0 + u * kOrderBlock + tid;
+                lk[u] = e < end ? lk[u] - kb : cn;
             }
 #pragma unroll
             for (int u = 0; u < kOrderSub; u++)
@@ -521,18 +541,25 @@ __global__ void __launch_bounds__(kOrderBlock)
         __syncthreads();
         for (uint32_t i = tid; i < cn; i += kOrderBlock) offsets[kb + i] = done + cur[i];
         for (uint32_t s0 = start; s0 < end; s0 += kSeg) {
+            // keys first, then records, from clamped indexes: the records
+            // are still in flight while the keys are ranked
             uint32_t lk[kOrderSub], rk[kOrderSub];
             float4 rv[kOrderSub];
 #pragma unroll
             for (int u = 0; u < kOrderSub; u++) {
                 const uint32_t e = s0 + u * kOrderBlock + tid;
-                lk[u] = kNoSlot;
-                rv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (e < end) {
-                    const uint32_t k = keys[e] - kb;
-                    lk[u] = k < cn ? k : kNoSlot;
-                    rv[u] = recs[e];
-                }
+                lk[u] = keys[e < end ? e : end - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kOrderSub; u++) {
+                const uint32_t e = s0 + u * kOrderBlock + tid, k = lk[u] - kb;
+                // (component-wise: a whole-struct copy put rv in scratch memory)
+                const float4 r = recs[e < end ? e : end - 1];
+                rv[u].x = r.x;
+                rv[u].y = r.y;
+                rv[u].z = r.z;
+                rv[u].w = r.w;
+                lk[u] = e < end && k < cn ? k : kNoSlot;
             }
             // multisplit by class: rank within the wavefront, count per (sub-tile, wavefront, class)
             if (tid < (uint32_t)kClassEntries) ccnt[tid] = 0;
@@ -729,19 +756,29 @@ static void radix_pass(const Src &src, int64_t n, int shift, uint32_t *hist, uin
 // First pass of the tracklet partition, over the low kBits of the bucket:
 // the histogram pass computes the keys once and leaves them in key_cache for
 // the scatter.
-template <int kBits>
-static void wide_pass_tkl(TklSrc src, int64_t n, int nd, uint32_t *key_cache, uint32_t *hist, uint32_t *hist_off,
+template <int kBits, typename Src>
+static void wide_pass_tkl(Src src, int64_t n, int nd, uint32_t *key_cache, uint32_t *hist, uint32_t *hist_off,
                           uint32_t *tiles, uint32_t *keys_out, float4 *recs_out, hipStream_t s)
 {
     constexpr int kT = kWideThreads<kBits>;
     const int64_t nblk = wide_blocks(n, kT);
     src.cached = nullptr;
-    hipLaunchKernelGGL((k_radix_hist<TklSrc, kBits, kT>), dim3((unsigned)nblk), dim3(kT), 0, s, src, n, 0, nd, hist,
+    hipLaunchKernelGGL((k_radix_hist<Src, kBits, kT>), dim3((unsigned)nblk), dim3(kT), 0, s, src, n, 0, nd, hist,
                        key_cache);
     launch_excl_scan(hist, nblk * nd, tiles, hist_off, s);
     src.cached = key_cache;
-    hipLaunchKernelGGL((k_wide_scatter<TklSrc, kBits, kT>), dim3((unsigned)nblk), dim3(kT), 0, s, src, n, 0, nd,
+    hipLaunchKernelGGL((k_wide_scatter<Src, kBits, kT>), dim3((unsigned)nblk), dim3(kT), 0, s, src, n, 0, nd,
                        hist_off, keys_out, recs_out);
+}
+
+template <typename Src>
+static void first_pass_tkl(const Src &src, int wide, int64_t n, int nd, uint32_t *key_cache, const BinBuffers &buf,
+                           uint32_t *keys_out, float4 *recs_out, hipStream_t s)
+{
+    if (wide == 10)
+        wide_pass_tkl<10>(src, n, nd, key_cache, buf.hist, buf.hist_off, buf.tiles_tkl, keys_out, recs_out, s);
+    else
+        wide_pass_tkl<kWideBits>(src, n, nd, key_cache, buf.hist, buf.hist_off, buf.tiles_tkl, keys_out, recs_out, s);
 }
 
 static int bit_length(uint64_t v)
@@ -785,13 +822,12 @@ void launch_bin(const float *y, const float *z, const float *dy, const uint32_t 
     const int nd = passes == 1 ? (int)n_slots + 1 : 1 << wide;
     if (n > 0) {
         // the other key buffer is free during the first pass
-        const TklSrc src{y, z, dy, det_row, grp, b, slot, nullptr};
-        if (wide == 10)
-            wide_pass_tkl<10>(src, n, nd, kdst[out ^ 1], buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
-                              rdst[out], s);
+        if (grp)
+            first_pass_tkl(TklSrc<true>{y, z, dy, det_row, grp, b, slot, nullptr}, wide, n, nd, kdst[out ^ 1], buf,
+                           kdst[out], rdst[out], s);
         else
-            wide_pass_tkl<kWideBits>(src, n, nd, kdst[out ^ 1], buf.hist, buf.hist_off, buf.tiles_tkl, kdst[out],
-                                     rdst[out], s);
+            first_pass_tkl(TklSrc<false>{y, z, dy, det_row, nullptr, b, slot, nullptr}, wide, n, nd, kdst[out ^ 1],
+                           buf, kdst[out], rdst[out], s);
         for (int p = 1; p < passes; p++) {
             const SlotPassSrc ps{kdst[out], rdst[out], slot};
             out ^= 1;

@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP translation units of libtrd.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -100,9 +101,22 @@ struct MatchIO {
     const void *rows_in;  // [n][kRowIn] of the state type
     void *rows_out;       // [n][kRowOut] of the state type
     int row_out;  // entries per result row: kRowOut, or kRowOutShort without chi2 per layer
-    // host side only: events recorded around the main match kernel (or null)
+    // host side only: events that take the main match kernel's start and end
+    // (or null)
     hipEvent_t ev_begin, ev_end;
 };
+
+// Launch of the main match kernel.  With the caller's events the dispatch
+// itself stamps them at the kernel's start and end, so no marker packet
+// sits between the kernel and its neighbours on the stream.
+template <typename K, typename... A>
+inline void launch_timed(const MatchIO &io, K kernel, dim3 grid, dim3 block, hipStream_t s, A... args)
+{
+    if (io.ev_begin)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0u, s, io.ev_begin, io.ev_end, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 // Rows of the ordered mode, in units of the state type.
 // in:  p[5], cov[15], x, sector, group (integers stored bit-exact), pad

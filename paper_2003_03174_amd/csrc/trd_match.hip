@@ -1229,11 +1229,11 @@ void launch_coop(int lanes, const DevCfg<float> &gf, const MatchIO &io, unsigned
                  hipStream_t s)
 {
     switch (lanes) {
-    case 4: hipLaunchKernelGGL((k_match_coop<TC, 4, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
-    case 16: hipLaunchKernelGGL((k_match_coop<TC, 16, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
-    case 32: hipLaunchKernelGGL((k_match_coop<TC, 32, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
-    case 64: hipLaunchKernelGGL((k_match_coop<TC, 64, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
-    default: hipLaunchKernelGGL((k_match_coop<TC, 8, kFloatCov>), dim3(grid), dim3(block), 0, s, gf, io); break;
+    case 4: launch_timed(io, k_match_coop<TC, 4, kFloatCov>, dim3(grid), dim3(block), s, gf, io); break;
+    case 16: launch_timed(io, k_match_coop<TC, 16, kFloatCov>, dim3(grid), dim3(block), s, gf, io); break;
+    case 32: launch_timed(io, k_match_coop<TC, 32, kFloatCov>, dim3(grid), dim3(block), s, gf, io); break;
+    case 64: launch_timed(io, k_match_coop<TC, 64, kFloatCov>, dim3(grid), dim3(block), s, gf, io); break;
+    default: launch_timed(io, k_match_coop<TC, 8, kFloatCov>, dim3(grid), dim3(block), s, gf, io); break;
     }
 }
 
@@ -1548,10 +1548,10 @@ void launch_beam_t(const DevCfg<TS> &g, const MatchIO &io, int n_hyp, hipStream_
 {
     const unsigned grid = (unsigned)((io.n * n_hyp + 255) / 256);
     switch (n_hyp) {
-    case 1: hipLaunchKernelGGL((k_match_beam<TS, TC, 1, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
-    case 2: hipLaunchKernelGGL((k_match_beam<TS, TC, 2, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
-    case 4: hipLaunchKernelGGL((k_match_beam<TS, TC, 4, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
-    default: hipLaunchKernelGGL((k_match_beam<TS, TC, 8, kFloatCov>), dim3(grid), dim3(256), 0, s, g, io); break;
+    case 1: launch_timed(io, k_match_beam<TS, TC, 1, kFloatCov>, dim3(grid), dim3(256), s, g, io); break;
+    case 2: launch_timed(io, k_match_beam<TS, TC, 2, kFloatCov>, dim3(grid), dim3(256), s, g, io); break;
+    case 4: launch_timed(io, k_match_beam<TS, TC, 4, kFloatCov>, dim3(grid), dim3(256), s, g, io); break;
+    default: launch_timed(io, k_match_beam<TS, TC, 8, kFloatCov>, dim3(grid), dim3(256), s, g, io); break;
     }
 }
 
@@ -1561,7 +1561,6 @@ void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &g
                  int n_hyp, hipStream_t s)
 {
     if (io.n <= 0) return;
-    if (io.ev_begin) (void)hipEventRecord(io.ev_begin, s);
     if (precision == 0) {
         launch_beam_t<double, double, false>(gd, io, n_hyp, s);
     } else if (precision == 2) {
@@ -1569,7 +1568,6 @@ void launch_beam(int precision, const DevCfg<double> &gd, const DevCfg<float> &g
     } else {
         launch_beam_t<float, float, true>(gf, io, n_hyp, s);
     }
-    if (io.ev_end) (void)hipEventRecord(io.ev_end, s);
     if (precision == 1) {
         switch (n_hyp) {
         case 1: hipLaunchKernelGGL(k_beam_fallback<1>, dim3(64), dim3(256), 0, s, gf, io); break;
@@ -2039,9 +2037,9 @@ void launch_lane(const DevCfg<TS> &g, const MatchIO &io, unsigned grid, int bloc
 {
     if (persistent) {
         const unsigned pg = persistent_grid<TS, TC, kFloatCov>(block, n_cu, grid);
-        hipLaunchKernelGGL((k_match_persistent<TS, TC, kFloatCov>), dim3(pg), dim3(block), 0, s, g, io);
+        launch_timed(io, k_match_persistent<TS, TC, kFloatCov>, dim3(pg), dim3(block), s, g, io);
     } else {
-        hipLaunchKernelGGL((k_match<TS, TC, kFloatCov>), dim3(grid), dim3(block), 0, s, g, io);
+        launch_timed(io, k_match<TS, TC, kFloatCov>, dim3(grid), dim3(block), s, g, io);
     }
 }
 
@@ -2050,7 +2048,6 @@ void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &
 {
     if (io.n <= 0) return;
     const unsigned grid = (unsigned)((io.n + block - 1) / block);
-    if (io.ev_begin) (void)hipEventRecord(io.ev_begin, s);
     if (precision == 0) {
         launch_lane<double, double, false>(gd, io, grid, block, persistent, n_cu, s);
     } else if (precision == 2) {
@@ -2064,7 +2061,6 @@ void launch_match(int precision, const DevCfg<double> &gd, const DevCfg<float> &
         else
             launch_coop<float, true>(lanes, gf, io, grid, block, s);
     }
-    if (io.ev_end) (void)hipEventRecord(io.ev_end, s);
     if (precision == 1) hipLaunchKernelGGL(k_match_fallback, dim3(64), dim3(256), 0, s, gf, io);
 }
 
