@@ -150,8 +150,9 @@ struct TklSrc {
     }
 };
 
-// First pass of the track sort: the seed's order key, its index as value.
-template <typename TS>
+// First pass of the track sort: the seed's order key, its index as value
+// (kGrouped: a group per seed in igrp, else all in group 0 and igrp unread).
+template <typename TS, bool kGrouped>
 struct TrkSrc {
     const TS *ip;
     const int32_t *isec, *igrp;
@@ -161,7 +162,7 @@ struct TrkSrc {
     __device__ __forceinline__ uint32_t sort_key(uint32_t k) const { return k; }
     __device__ __forceinline__ uint32_t key(int64_t e) const
     {
-        return track_order_key(ip[e], ip[n + e], ip[4 * n + e], isec[e], igrp ? igrp[e] : 0, n_groups);
+        return track_order_key(ip[e], ip[n + e], ip[4 * n + e], isec[e], kGrouped ? igrp[e] : 0, n_groups);
     }
     __device__ __forceinline__ void load(int64_t e, uint32_t &k, uint32_t &rec) const
     {
@@ -195,7 +196,13 @@ struct SlotPassSrc {
     __device__ __forceinline__ void load(int64_t e, uint32_t &k, float4 &rec) const
     {
         k = keys[e];
-        rec = recs[e];
+        // component-wise: a whole-struct copy puts the caller's record array
+        // in scratch memory
+        const float4 r = recs[e];
+        rec.x = r.x;
+        rec.y = r.y;
+        rec.z = r.z;
+        rec.w = r.w;
     }
 };
 
@@ -262,15 +269,14 @@ __global__ void __launch_bounds__(kBlock)
     for (int q = 0; q < kSub * kWaves; q++) cnt[q][tid] = 0;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)tile * kSortTile;
-    // all of this thread's elements in flight at once
+    // all of this thread's elements in flight at once (clamped indexes,
+    // n > 0; the lanes past the end take no part below)
     uint32_t kv[kSub];
     Rec rv[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; j++) {
         const int64_t e = base + j * kBlock + tid;
-        kv[j] = 0;
-        rv[j] = Rec{};
-        if (e < n) src.load(e, kv[j], rv[j]);
+        src.load(e < n ? e : n - 1, kv[j], rv[j]);
     }
     __syncthreads();
     // rank within the wavefront; the first lane of each digit records its count
@@ -863,8 +869,12 @@ static void track_sort(const TS *ip, const int32_t *isec, const int32_t *igrp, i
     const int passes = radix_passes((uint64_t)(n_groups * kSectors) << kOrderPosBits);
     uint32_t *kb[2] = {o.key_a, o.key_b};
     uint32_t *vb[2] = {o.val_a, o.val_b};
-    radix_pass(TrkSrc<TS>{ip, isec, igrp, n, n_groups}, n, 0, o.hist, o.hist_off, o.tiles, kb[0], vb[0], s,
-               passes == 1 ? o.rank : nullptr);
+    if (igrp)
+        radix_pass(TrkSrc<TS, true>{ip, isec, igrp, n, n_groups}, n, 0, o.hist, o.hist_off, o.tiles, kb[0], vb[0],
+                   s, passes == 1 ? o.rank : nullptr);
+    else
+        radix_pass(TrkSrc<TS, false>{ip, isec, nullptr, n, n_groups}, n, 0, o.hist, o.hist_off, o.tiles, kb[0],
+                   vb[0], s, passes == 1 ? o.rank : nullptr);
     int cur = 0;
     for (int p = 1; p < passes; p++) {
         radix_pass(PassSrc<uint32_t>{kb[cur], vb[cur]}, n, p * kRadixBits, o.hist, o.hist_off, o.tiles,

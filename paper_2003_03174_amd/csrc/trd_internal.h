@@ -173,18 +173,18 @@ void launch_voxel_solve(const double *sums, int nvox, int min_count, float *dist
 template <typename TS>
 __device__ __forceinline__ uint32_t track_order_key(TS y, TS z, TS c, int sec, int grp, int32_t n_groups)
 {
-    uint32_t k = (uint32_t)(n_groups * kSectors) << kOrderPosBits;
-    if (sec >= 0 && sec < kSectors && grp >= 0 && grp < n_groups && __builtin_isfinite(y) &&
-        __builtin_isfinite(z)) {
-        const TS zs = (z + TS(512)) * TS(0.03125), ys = (y + TS(64)) * TS(0.125);
-        const int zb = zs < TS(0) ? 0 : (zs >= TS(31) ? 31 : (int)zs);
-        const int yb = ys < TS(0) ? 0 : (ys >= TS(15) ? 15 : (int)ys);
-        const TS ac = fabs(c);
-        const int pb = ac < TS(0.8) ? 0 : (ac < TS(1.6) ? 1 : (ac < TS(2.5) ? 2 : 3));
-        k = ((uint32_t)(grp * kSectors + sec) << kOrderPosBits) | ((uint32_t)pb << 9) | ((uint32_t)zb << 4) |
-            (uint32_t)yb;
-    }
-    return k;
+    // without branches, so that the loads of several seeds can be in flight
+    // at once (the bins of a seed that is not valid are computed and dropped)
+    const bool ok = (sec >= 0) & (sec < kSectors) & (grp >= 0) & (grp < n_groups) & __builtin_isfinite(y) &
+                    __builtin_isfinite(z);
+    const TS zs = (z + TS(512)) * TS(0.03125), ys = (y + TS(64)) * TS(0.125);
+    const uint32_t zb = (uint32_t)(int)fmin(fmax(zs, TS(0)), TS(31));
+    const uint32_t yb = (uint32_t)(int)fmin(fmax(ys, TS(0)), TS(15));
+    const TS ac = fabs(c);
+    const uint32_t pb = (uint32_t)!(ac < TS(0.8)) + (uint32_t)!(ac < TS(1.6)) + (uint32_t)!(ac < TS(2.5));
+    const uint32_t k = ((uint32_t)(grp * kSectors + sec) << kOrderPosBits) | (pb << 9) | (zb << 4) | yb;
+    const uint32_t m = 0u - (uint32_t)ok;
+    return (k & m) | (((uint32_t)(n_groups * kSectors) << kOrderPosBits) & ~m);
 }
 
 // buffers of the spatial track order (capacity n each unless noted)
