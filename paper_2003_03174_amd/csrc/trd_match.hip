@@ -1880,8 +1880,10 @@ __global__ void __launch_bounds__(256) k_voxel_solve(const double *sums, int nvo
     reinterpret_cast<float4 *>(dist)[v] = o;
 }
 
-// input track i -> state row rank[i] (coalesced reads, one row per lane)
-template <typename TS>
+// input track i -> state row rank[i] (coalesced reads, one row per lane;
+// kGrouped: groups read from io.igrp, else 0, so that no load is behind a
+// branch)
+template <typename TS, bool kGrouped>
 __global__ void __launch_bounds__(256) k_track_pack(MatchIO io, const uint32_t *rank, TS *rows)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1897,7 +1899,7 @@ __global__ void __launch_bounds__(256) k_track_pack(MatchIO io, const uint32_t *
     for (int k = 0; k < 15; k++) v[5 + k] = ic[k * n + i];
     v[20] = ix[i];
     v[21] = as_row(io.isec[i], TS());
-    v[22] = as_row(io.igrp ? io.igrp[i] : 0, TS());
+    v[22] = as_row(kGrouped ? io.igrp[i] : 0, TS());
     v[23] = TS(0);
     TS *r = rows + (int64_t)rank[i] * kRowIn;
 #pragma unroll
@@ -1944,8 +1946,12 @@ void order_in(MatchIO &io, int32_t n_groups, const TrackOrder &o, hipStream_t s)
 {
     const int64_t n = io.n;
     launch_track_sort(sizeof(TS) == 8 ? 0 : 1, io.ip, io.isec, io.igrp, n, n_groups, o, s);
-    hipLaunchKernelGGL(k_track_pack<TS>, dim3(blocks_for(n)), dim3(256), 0, s, io, (const uint32_t *)o.rank,
-                       reinterpret_cast<TS *>(o.rows_in));
+    if (io.igrp)
+        hipLaunchKernelGGL((k_track_pack<TS, true>), dim3(blocks_for(n)), dim3(256), 0, s, io,
+                           (const uint32_t *)o.rank, reinterpret_cast<TS *>(o.rows_in));
+    else
+        hipLaunchKernelGGL((k_track_pack<TS, false>), dim3(blocks_for(n)), dim3(256), 0, s, io,
+                           (const uint32_t *)o.rank, reinterpret_cast<TS *>(o.rows_in));
     io.rows_in = o.rows_in;
     io.rows_out = o.rows_out;
     io.row_out = io.ochi2l ? kRowOut : kRowOutShort;
