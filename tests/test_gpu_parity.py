@@ -28,13 +28,14 @@ def workload(name, **kw):
     return _cache[key]
 
 
-def run_gpu(w, prec, block_size=0, params=None, search_lanes=0, flags=0):
+def run_gpu(w, prec, block_size=0, params=None, search_lanes=0, flags=0, groups=True):
+    """groups=False passes no group arrays (every tracklet and seed in group 0)."""
     P = params or w["params"]
     lay = synth.to_device_layout(w)
     d = B.device_inputs(lay, prec)
     m = B.Matcher(P, prec, block_size=block_size, search_lanes=search_lanes, flags=flags)
-    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
-    out = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"])
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"] if groups else None, w["n_groups"])
+    out = m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"] if groups else None)
     torch.cuda.synchronize()
     res = pu.to_numpy(out)
     off, srt = m.binning()
@@ -322,6 +323,77 @@ def test_invalid_tracklets_and_bad_seeds():
     assert np.all(ref["status"][:3] == B.TRK_BAD_INPUT)
     rep = pu.compare(ref, res, "fp32")
     assert rep.ok, rep.summary()
+
+
+def _with_edge_values(w):
+    """Tracklets and seeds at the edges of the cell key's and the seeds'
+    order key's domains."""
+    w = dict(w)
+    for k in ("tkl_y", "tkl_z", "tkl_dy", "tkl_det_row", "tkl_group", "p", "sector", "group"):
+        w[k] = w[k].copy()
+    y, z, dy, dr, tg = w["tkl_y"], w["tkl_z"], w["tkl_dy"], w["tkl_det_row"], w["tkl_group"]
+    # non-finite: dropped; finite far outside the bins' span: the outer bins
+    y[0], y[1], y[2], y[3] = np.inf, -np.inf, 1e30, -1e30
+    z[4], z[5] = np.nan, np.inf
+    dy[6], dy[7], dy[8], dy[9] = np.nan, -np.inf, 1e30, -1e30
+    # the last chamber slot and row (kept); chamber 540 and an all-ones word (dropped)
+    dr[10] = (539 << 5) | (w["params"]["n_rows"] - 1)
+    dr[11] = 540 << 5
+    dr[12] = 0xFFFFFFFF
+    ng = w["n_groups"]
+    if ng > 1:
+        tg[13], tg[14], tg[15] = -1, ng, 1 << 30
+    # seeds: non-finite z and q/pT, a sector and (with groups) a group out of
+    # range are bad input; y and z beyond the order key's bins are clamped
+    p = w["p"]
+    p[1, 0] = np.nan
+    p[4, 1] = np.inf
+    w["sector"][2] = -1
+    if ng > 1:
+        w["group"][3] = ng
+    p[0, 4] = 80.0
+    p[0, 5] = -100.0
+    p[1, 6] = 600.0
+    return w
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_edge_values_of_binning_and_order(grouped):
+    """Infinities, NaN, finite values far outside the bins' span, chambers,
+    rows and groups out of range, in the tracklets and in the seeds: binning
+    bit-exact against the oracle, results against the oracle.  Without
+    groups, passing no group arrays gives the binning and results of
+    zero-filled ones bit for bit, in separate calls and in the fused one."""
+    params = dict(dy_bin_w=0.125, n_db=64)
+    if grouped:
+        w = synth.generate_frames(43, 3, [700, 500, 900], [0.5, 0.3, 0.7], params_over=params)
+    else:
+        w = workload(None, n_tracks=2000, seed=41, fake_ratio=0.5, params=params)
+    w = _with_edge_values(w)
+    res = run_gpu(w, "fp32")
+    check_binning(w, res)
+    ref = O.match(w["params"], w, threads=0, margins=pu.MARGINS["fp32"])
+    bad = (0, 1, 2, 3) if grouped else (0, 1, 2)
+    for i in bad:
+        assert ref["status"][i] == B.TRK_BAD_INPUT and res["status"][i] & B.TRK_BAD_INPUT, i
+    rep = pu.compare(ref, res, "fp32")
+    print(rep.summary())
+    assert rep.ok, rep.summary()
+    if grouped:
+        return
+    keys = ("idx", "p", "cov", "x", "sector", "chi2", "chi2_layer", "n_match", "status", "offsets", "sorted")
+    res0 = run_gpu(w, "fp32", groups=False)
+    for k in keys:
+        assert np.array_equal(res0[k], res[k], equal_nan=True), k
+    d = B.device_inputs(synth.to_device_layout(w), "fp32")
+    m = B.Matcher(w["params"], "fp32")
+    out = m.load_and_match(d["y"], d["z"], d["dy"], d["det_row"], None, 1, d["p"], d["cov"], d["x"],
+                           d["sector"], tgroup=None)
+    torch.cuda.synchronize()
+    fused = pu.to_numpy(out)
+    m.close()
+    for k in keys[:-2]:
+        assert np.array_equal(fused[k], res[k], equal_nan=True), k
 
 
 def test_deterministic_repeats():
