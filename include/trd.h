@@ -234,9 +234,9 @@ int trd_create(const trd_config *cfg, int device, trd_ctx **out);
  * Errors: TRD_EINVAL, TRD_ENOMEM, TRD_EBUDGET. */
 int trd_reserve(trd_ctx *ctx, int64_t max_tracklets, int32_t max_groups, int64_t max_tracks);
 
-/* Prepares the search of Sect. 3 of the paper ("all tracklets inside a
- * search road based on the covariance matrices", only tracklets of the same
- * interaction, Sect. 4): bins the tracklets into (group, chamber, dy bin,
+/* Prepares the search of Sect. 3 of the paper (every tracklet within a road
+ * sized from the track and tracklet covariances, and from the track's own
+ * interaction only, Sect. 4): bins the tracklets into (group, chamber, dy bin,
  * y bin, pad row) cells (pad rows innermost, so the cells of one (dy bin,
  * y bin) that overlap a road are contiguous): exact cell keys, a stable sort
  * by (cell, input index) into ctx-owned sorted storage, which replaces the

@@ -11,11 +11,10 @@
  *   for every seed track (independently; the paper parallelises over tracks)
  *     for layer l = 0..5
  *       propagate the helix state and covariance to the layer radius
- *       (the "maximal precision" step of Sect. 3, here a uniform field);
+ *       (the most precise extrapolation step of Sect. 3, here a uniform field);
  *       rotate into the neighbouring sector if the point left the sector;
  *       add multiple scattering of the layer;
- *       open a search road from the covariance (Sect. 3, tracklets "inside a
- *       search road based on the covariance matrices");
+ *       open a search road sized from the covariances (Sect. 3);
  *       for every tracklet in the road: linear extrapolation to the
  *       tracklet radius, pad-tilt corrected y residual (Sect. 3, last
  *       paragraph), dy exclusion beyond 4 sigma, chi2 from y and z only;
@@ -255,7 +254,7 @@ static int rk_deriv(const ocfg *g, double x, const double v[3], double t, double
 
 /* Helix step in the sector frame from *x to x2 with its Jacobian applied to
  * C (if given).  Uniform field: the closed form (M1, M2).  Field map: the
- * "maximal precision" step of Sect. 3 as a classical 4th-order Runge-Kutta
+ * most precise extrapolation step of Sect. 3 as a classical 4th-order Runge-Kutta
  * integration of y' = tan(phi), z' = tan(lambda)/cos(phi), sin(phi)' =
  * -kappa Bz(r, z) q/pT over equal x steps of at most field_step; the
  * covariance is transported with the exact helix Jacobian over the whole
