@@ -108,14 +108,25 @@ struct MatchIO {
 
 // Launch of the main match kernel.  With the caller's events the dispatch
 // itself stamps them at the kernel's start and end, so no marker packet
-// sits between the kernel and its neighbours on the stream.
+// sits between the kernel and its neighbours on the stream; a stream under
+// graph capture records them around the kernel instead (event nodes).
 template <typename K, typename... A>
 inline void launch_timed(const MatchIO &io, K kernel, dim3 grid, dim3 block, hipStream_t s, A... args)
 {
-    if (io.ev_begin)
-        hipExtLaunchKernelGGL(kernel, grid, block, 0u, s, io.ev_begin, io.ev_end, 0u, args...);
-    else
-        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    if (io.ev_begin) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+            (void)hipGetLastError();  // a refused query leaves no error for the call to report
+            cap = hipStreamCaptureStatusActive;
+        }
+        if (cap == hipStreamCaptureStatusNone) {
+            hipExtLaunchKernelGGL(kernel, grid, block, 0u, s, io.ev_begin, io.ev_end, 0u, args...);
+            return;
+        }
+    }
+    if (io.ev_begin) (void)hipEventRecord(io.ev_begin, s);
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    if (io.ev_end) (void)hipEventRecord(io.ev_end, s);
 }
 
 // Rows of the ordered mode, in units of the state type.

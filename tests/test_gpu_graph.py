@@ -70,6 +70,35 @@ def test_graph_replays_equal_eager(prec, flags):
     m.close()
 
 
+def test_graph_of_a_timed_matcher():
+    """A matcher that times its match kernel (TRD_CFG_TIME_KERNEL) is timed by
+    the kernel's own dispatch when eager and can still be captured (its events
+    are then recorded around the kernel); replays give the eager results."""
+    w = synth.generate("c2_frame_20k")
+    d = B.device_inputs(synth.to_device_layout(w), "fp32")
+    n = w["n_tracks"]
+    m = B.Matcher(w["params"], "fp32", flags=B.TRD_CFG_TIME_KERNEL)
+    m.reserve(w["n_tracklets"], w["n_groups"], n)
+    out = m.alloc_results(n)
+    m.load(d["y"], d["z"], d["dy"], d["det_row"], d["tgroup"], w["n_groups"])
+    m.match(d["p"], d["cov"], d["x"], d["sector"], d["group"], out=out)
+    torch.cuda.synchronize()
+    t = m.kernel_times()
+    assert len(t) == 1 and 0.0 < t[0] < 100.0, t
+    eager = {k: v.cpu().numpy() for k, v in _snapshot(out).items() if v is not None}
+    g = _capture(m, d, w["n_groups"], out)
+    for rep in range(3):
+        for v in out.values():
+            if v is not None:
+                v.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        for k in eager:
+            assert np.array_equal(got[k], eager[k], equal_nan=True), (rep, k)
+    m.close()
+
+
 def test_multiframe_batch_graph_full_size_sampled():
     """64 frames (~1.4M tracks, ~12M tracklets) replayed as one graph, float
     path; 2,000 sampled tracks against the oracle, group isolation in full."""
