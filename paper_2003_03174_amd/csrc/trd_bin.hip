@@ -124,8 +124,9 @@ struct KeyDiv {
 };
 
 // Sources of the sort passes.  Each stores a full key and sorts by
-// sort_key(key).  First pass of the tracklet partition: the caller's
-// arrays, key and record computed on the fly, sorted by bucket.
+// sort_key(key).  First pass of the tracklet partition: the histogram
+// computes each key from the caller's arrays and keeps it, the scatter reads
+// that key and builds the record from the caller's arrays, sorted by bucket.
 // Later passes: the previous pass's keys and records.
 // kGrouped: a group per tracklet in grp (else every tracklet is in group 0
 // and grp is not read); a compile-time choice, so that no load is behind a branch
