@@ -107,9 +107,9 @@ struct MatchIO {
 };
 
 // Launch of the main match kernel.  With the caller's events the dispatch
-// itself stamps them at the kernel's start and end, so no marker packet
-// sits between the kernel and its neighbours on the stream; a stream under
-// graph capture records them around the kernel instead (event nodes).
+// itself stamps them at the kernel's start and end, in place of an event
+// record on each side (which left longer gaps around the kernel); a stream
+// under graph capture records them around the kernel instead (event nodes).
 template <typename K, typename... A>
 inline void launch_timed(const MatchIO &io, K kernel, dim3 grid, dim3 block, hipStream_t s, A... args)
 {
